@@ -1,0 +1,98 @@
+"""Pins of the refinement criterion and of the MLUPS count.
+
+Vorticity of a linear velocity field is its constant curl, in root-cell units on
+every level (Sec. "Adaptive Mesh Refinement" of the solver); the relative
+threshold tags exactly the blocks above theta * max; the AMR-weighted update
+count of Sec. "Solver Performance" on hand-counted meshes."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_08085_amd import workloads as W
+
+
+def _set_linear_field(o, case, A, level_blocks, mesh):
+    dim = case.dim
+    for B in level_blocks:
+        L = int(mesh["level"][B])
+        s = 1 << (case.lmax - 1 - L)
+        W0 = 4 << (case.lmax - 1)
+        f = np.zeros((case.mb, case.q))
+        for l in range(case.mb):
+            idx = (l & 3, (l >> 2) & 3, l >> 4)
+            # cell centre in root-cell units
+            x = np.array([(mesh["X"][B, a] + s * idx[a] + 0.5 * s) * 4.0 / W0 for a in range(dim)])
+            f[l] = oracle.feq(dim, case.q, 1.0, A @ x)
+        o.set_block_f(B, f)
+
+
+@pytest.mark.parametrize("dim,q,lvl", [(2, 9, 0), (2, 9, 1), (3, 19, 0), (3, 27, 1)])
+def test_vorticity_of_linear_field(dim, q, lvl):
+    rng = np.random.default_rng(13)
+    case = W.cavity(dim, q, 16 if dim == 2 else 8, 2, 100.0, cap=400)
+    o = oracle.Oracle(case)
+    if lvl == 1:
+        t = np.ones(case.cap, np.int8)
+        o.tag(tags_in=t)
+        o.adapt()
+    m = o.mesh()
+    A = rng.uniform(-1e-3, 1e-3, size=(dim, dim))
+    _set_linear_field(o, case, A, m["ids"][lvl], m)
+    o.tag(kind=0, theta=0.1)
+    crit = o.crit()
+    if dim == 2:
+        exact = abs(A[1, 0] - A[0, 1])
+    else:
+        exact = np.sqrt((A[2, 1] - A[1, 2]) ** 2 + (A[0, 2] - A[2, 0]) ** 2 + (A[1, 0] - A[0, 1]) ** 2)
+    leaves = m["ids"][lvl]
+    # u = A x is computed from feq, so it is linear to rounding; f-based u has ~1e-16 error
+    assert np.abs(crit[leaves] - exact).max() < 1e-12
+    assert np.all(crit[m["ids"][0]] == -1.0) if lvl == 1 else True
+
+
+def test_relative_threshold_tags():
+    case = W.cavity(2, 9, 16, 3, 100.0, cap=400)
+    o = oracle.Oracle(case)
+    m = o.mesh()
+    # shear only in the top row of blocks: u_x = a (y - 12) for y > 12
+    for B in range(case.nroot):
+        f = np.zeros((16, 9))
+        for l in range(16):
+            y = (m["X"][B, 1] // 4) + ((l >> 2) & 3) + 0.5  # root cells (W0 = 16 finest)
+            ux = 1e-3 * max(y - 12.0, 0.0) ** 2
+            f[l] = oracle.feq(2, 9, 1.0, [ux, 0.0])
+        o.set_block_f(B, f)
+    tags = o.tag(kind=0, theta=0.1)
+    crit = o.crit()
+    wmax = crit[: case.nroot].max()
+    exp = (crit[: case.nroot] > 0.1 * wmax).astype(np.int8)
+    assert np.array_equal(tags[: case.nroot], exp)
+    assert 0 < exp.sum() < case.nroot
+
+
+def test_distance_tags():
+    # 2-D channel 64 x 32 cells, 8x8-cell cylinder at x = 16; d_spec = 10 root cells
+    case = W.cylinder(2, 9, (64, 32), 8, 16, 3, 100.0, cap=800)
+    o = oracle.Oracle(case)
+    tags = o.tag(kind=1, d_spec=10.0, freeze=1)
+    m = o.mesh()
+    for B in range(case.nroot):
+        if case.solid[B]:
+            assert tags[B] == 0
+            continue
+        x0, y0 = m["X"][B, 0] // 4, m["X"][B, 1] // 4  # root cells
+        # distance box-to-box to the cylinder [16,24)x[12,20) and to the outflow x = 64
+        dx = max(16 - (x0 + 4), x0 - 24, 0)
+        dy = max(12 - (y0 + 4), y0 - 20, 0)
+        d = min(np.hypot(dx, dy), 64 - (x0 + 4))
+        want = 2 if d < 10.0 else 0
+        assert tags[B] == want, (B, d)
+
+
+def test_mlups_update_count_hand_counted():
+    # 2-D, 4 root blocks, one refined (4 children), one of those refined again
+    assert W.mlups_updates([4], 2) == 4 * 16
+    assert W.mlups_updates([4, 4], 2) == (4 * 16 - 16) + 2 * 4 * 16
+    assert W.mlups_updates([4, 4, 4], 2) == (64 - 16) + 2 * (64 - 16) + 4 * 64
+    # 3-D, 8 roots, 2 refined
+    assert W.mlups_updates([8, 16], 3) == (8 * 64 - 2 * 64) + 2 * 16 * 64
