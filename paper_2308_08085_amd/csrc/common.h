@@ -1,0 +1,144 @@
+// common.h -- device-side definitions shared by the HIP kernels of the AMR-LBM
+// library: lattices, storage formats, the device view of the forest and the
+// kernel parameter blocks.  gfx950 (CDNA4), wave64.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/amr_lbm.h"
+
+namespace amr {
+
+constexpr int kNone = -1;
+constexpr int kNSkip = -2;
+constexpr int kSolid = -9;
+constexpr int kMaxLevels = 8;
+
+enum : int8_t {
+    ST_UNREF = 0, ST_REF = 1, ST_REF_CHILD = 2, ST_REF_PERM = 3, ST_NEW = 6, ST_REMOVE = 7, ST_INACTIVE = 8
+};
+__host__ __device__ inline bool is_refined(int s) { return s == ST_REF || s == ST_REF_CHILD || s == ST_REF_PERM; }
+
+// per-block flags kept by the connectivity rebuild
+enum : uint8_t { BF_NSKIP = 1, BF_BOUNDARY = 2, BF_PARENT_MASK = 4 };
+
+// ---------------------------------------------------------------------------
+// Velocity sets, numbered as in the paper's velocity-set figure.  3-D uses one
+// 27-entry table (D3Q19 = its first 19 entries); 2-D its own 9-entry table.
+// Weights are the standard quadrature weights.
+// direction vectors, (x, y, z) per direction
+constexpr int8_t kVec2[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+                                {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+constexpr int8_t kVec3[27][3] = {
+    {0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},    {0, -1, 0},  {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},   {-1, -1, 0}, {1, 0, 1},   {-1, 0, -1},  {0, 1, 1},   {0, -1, -1}, {1, -1, 0},
+    {-1, 1, 0},  {1, 0, -1},  {-1, 0, 1},  {0, 1, -1},   {0, -1, 1},  {1, 1, 1},  {-1, -1, -1},
+    {1, 1, -1},  {-1, -1, 1}, {1, -1, 1},  {-1, 1, -1},  {-1, 1, 1},  {1, -1, -1}};
+
+struct D2 {
+    static constexpr int D = 2, NB = 9, MB = 16, NC = 4;
+    __host__ __device__ static constexpr int cx(int p) { return kVec2[p][0]; }
+    __host__ __device__ static constexpr int cy(int p) { return kVec2[p][1]; }
+    __host__ __device__ static constexpr int cz(int) { return 0; }
+};
+struct D3 {
+    static constexpr int D = 3, NB = 27, MB = 64, NC = 8;
+    __host__ __device__ static constexpr int cx(int p) { return kVec3[p][0]; }
+    __host__ __device__ static constexpr int cy(int p) { return kVec3[p][1]; }
+    __host__ __device__ static constexpr int cz(int p) { return kVec3[p][2]; }
+};
+
+template <int Q> struct Lat;
+template <> struct Lat<9> : D2 {
+    static constexpr int Q = 9;
+    __host__ __device__ static constexpr double w(int p) { return p == 0 ? 4.0 / 9.0 : (p < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+    __host__ __device__ static constexpr int opp(int p) { return p == 0 ? 0 : (p < 5 ? 1 + ((p + 1) & 3) : 5 + ((p - 3) & 3)); }
+};
+template <> struct Lat<19> : D3 {
+    static constexpr int Q = 19;
+    __host__ __device__ static constexpr double w(int p) { return p == 0 ? 1.0 / 3.0 : (p < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+    __host__ __device__ static constexpr int opp(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
+};
+template <> struct Lat<27> : D3 {
+    static constexpr int Q = 27;
+    __host__ __device__ static constexpr double w(int p) {
+        return p == 0 ? 8.0 / 27.0 : (p < 7 ? 2.0 / 27.0 : (p < 19 ? 1.0 / 54.0 : 1.0 / 216.0));
+    }
+    __host__ __device__ static constexpr int opp(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
+};
+
+// index of the neighbour region with per-axis offsets r in {-1,0,1}, as a
+// position 0..26 in (x fastest) offset order; LDS link tables are kept in this
+// order so kernels can look links up arithmetically
+__host__ __device__ inline int offset_slot(int rx, int ry, int rz) { return (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1); }
+
+// ---------------------------------------------------------------------------
+// Storage formats.  Shifted forms keep g = f - w; arithmetic in R.
+template <int S> struct Store;
+template <> struct Store<AMR_F64> {
+    using T = double; using R = double; static constexpr bool shift = false;
+    __device__ static R ld(const T *p) { return *p; }
+    __device__ static void st(T *p, R v) { *p = v; }
+};
+template <> struct Store<AMR_F32> {
+    using T = float; using R = float; static constexpr bool shift = false;
+    __device__ static R ld(const T *p) { return *p; }
+    __device__ static void st(T *p, R v) { *p = v; }
+};
+template <> struct Store<AMR_F32S> {
+    using T = float; using R = float; static constexpr bool shift = true;
+    __device__ static R ld(const T *p) { return *p; }
+    __device__ static void st(T *p, R v) { *p = v; }
+};
+template <> struct Store<AMR_F16S> {
+    using T = __half; using R = float; static constexpr bool shift = true;
+    __device__ static R ld(const T *p) { return __half2float(*p); }
+    __device__ static void st(T *p, R v) { *p = __float2half_rn(v); }
+};
+template <> struct Store<AMR_BF16S> {
+    using T = __hip_bfloat16; using R = float; static constexpr bool shift = true;
+    __device__ static R ld(const T *p) { return __bfloat162float(*p); }
+    __device__ static void st(T *p, R v) { *p = __float2bfloat16(v); }
+};
+
+inline size_t storage_bytes(int s) { return s == AMR_F64 ? 8 : (s == AMR_F16S || s == AMR_BF16S ? 2 : 4); }
+
+// ---------------------------------------------------------------------------
+// Device view of the forest.  Block metadata is structure-of-arrays: entry p
+// of block B lives at [p * cap + B] (the paper's kappa + p N_blocks layout);
+// distributions at [q * capc + B * Mb + l].
+struct DevMesh {
+    int32_t cap;
+    int64_t capc;
+    int32_t lmax;
+    int32_t *nbr, *nbrc, *X;
+    int8_t *level, *status, *tag, *ldes, *viol;
+    uint8_t *bflag;
+    uint64_t *gmask, *imask;  // ghost / interface cell bitmasks (bit l)
+};
+
+struct BCParams {
+    int32_t kind[6];
+    double u[6][3];
+};
+
+struct LevelParams {
+    int32_t par[kMaxLevels];     // buffer holding each level's current data
+    double omega[kMaxLevels];
+    double r_cf[kMaxLevels];     // coarse->fine rescaling of level L -> L+1
+    double r_fc[kMaxLevels];     // fine->coarse rescaling of level L+1 -> L
+};
+
+// XCD-aware workgroup order: dispatch places workgroup w on XCD (w mod 8);
+// give each XCD a contiguous range of work so neighbouring blocks share an L2.
+__device__ inline int xcd_remap(int wg, int nwg) {
+    int per = nwg >> 3;
+    int full = per << 3;
+    if (wg >= full) return wg;
+    return (wg & 7) * per + (wg >> 3);
+}
+
+}  // namespace amr

@@ -1,0 +1,82 @@
+// kernels.h -- host-side launchers of the HIP kernels (implemented in
+// lbm_kernels.hip and mesh_kernels.hip), called by the runtime.
+#pragma once
+
+#include "common.h"
+
+namespace amr {
+
+struct DevCounters {
+    int32_t nids[kMaxLevels];
+    int32_t niface[kMaxLevels];
+    int32_t gtop;
+    int32_t n_ref, n_coa, n_rev;
+    int32_t nfreed;
+    int32_t n_out;
+    int32_t pad[2];
+    unsigned long long wmax_bits;
+    int32_t totals[kMaxLevels];
+    int32_t bases[kMaxLevels];
+    double mass[4];
+};
+
+// everything a launcher needs: device views and scratch carved from the arena
+struct Ctx {
+    DevMesh m;
+    int dim, q, nb, mb, nc, storage;
+    int nroot;
+    int root[3];
+    int periodic[3];
+    int face_prio[6];
+    int face_kind[6];
+    void *f[2];
+    int32_t *ids;        // [lmax][cap]
+    int32_t *ids_tmp;    // [lmax][cap]
+    int32_t *iface;      // [lmax][cap]
+    int32_t *gap;        // [cap]
+    int32_t *first;      // [cap]
+    int32_t *rank;       // [lmax * cap]
+    int32_t *rlist;      // [cap]
+    int32_t *clist;      // [cap]
+    int8_t *bins;        // [lmax * cap]
+    int32_t *scan_part;  // [nwg_max * 8]
+    int32_t *cnt;        // [cap]
+    int32_t *off;        // [cap]
+    double *crit;        // [cap]
+    double *part4;       // [cap * 4]
+    uint8_t *solid;      // [nroot]
+    int32_t *solid_list; // [nroot]
+    int32_t n_solid;
+    DevCounters *ctr;
+    void *staging;
+    size_t staging_bytes;
+    hipStream_t stream;
+};
+
+// ---- LBM kernels (lbm_kernels.hip) ----
+void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp,
+                           const BCParams &bc);
+// mode 0: ghost cells of children with an N_SKIP link; 1: every cell of every child
+void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells);
+// mode 0: interface parent cells; 1: every parent cell (non-refined entries are skipped)
+void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells);
+void launch_fill_rest(const Ctx &c);
+void launch_set_rho_u_root(const Ctx &c, const double *rho_u_dev, int cell0, int ncells);
+void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp);
+void launch_block_f(const Ctx &c, int set, int b0, int b1, double *stage, const LevelParams &lp);
+void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, void *stage, const LevelParams &lp);
+void launch_mass(const Ctx &c, const LevelParams &lp);
+
+// ---- mesh kernels (mesh_kernels.hip) ----
+void launch_init_mesh(const Ctx &c);
+void launch_crit_reset(const Ctx &c);
+void launch_tag_vorticity(const Ctx &c, double theta);
+void launch_tag_distance(const Ctx &c, double d_spec, int freeze);
+void launch_effective_tags(const Ctx &c);
+// adaptation after the counts are known on the host
+void launch_adapt_assign(const Ctx &c, int n_ref);                 // S2 + S3
+void launch_adapt_build(const Ctx &c, int n_ref, const LevelParams &lp);  // S4 .. S7
+void launch_connectivity(const Ctx &c, int id_bound);             // S8 + masks + interface lists
+void launch_out_count(const Ctx &c);  // per-block output counts + exclusive offsets, n_out
+
+}  // namespace amr
