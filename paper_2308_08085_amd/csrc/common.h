@@ -75,6 +75,18 @@ template <> struct Lat<27> : D3 {
 // order so kernels can look links up arithmetically
 __host__ __device__ inline int offset_slot(int rx, int ry, int rz) { return (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1); }
 
+// region slot (in the lattice's own link-table numbering: 0..8 in 2-D,
+// 0..26 in 3-D) of a cell position given in local block coordinates that may
+// lie one cell outside the block
+template <typename Dd>
+__host__ __device__ inline int region_of(int x, int y, int z) {
+    const int rx = x < 0 ? -1 : (x > 3 ? 1 : 0);
+    const int ry = y < 0 ? -1 : (y > 3 ? 1 : 0);
+    const int rz = z < 0 ? -1 : (z > 3 ? 1 : 0);
+    return offset_slot(rx, ry, rz) - (Dd::D == 2 ? 9 : 0);
+}
+template <typename Dd> constexpr int kCenterSlot = Dd::D == 2 ? 4 : 13;
+
 // ---------------------------------------------------------------------------
 // Storage formats.  Shifted forms keep g = f - w; arithmetic in R.
 template <int S> struct Store;
@@ -107,13 +119,52 @@ template <> struct Store<AMR_BF16S> {
 inline size_t storage_bytes(int s) { return s == AMR_F64 ? 8 : (s == AMR_F16S || s == AMR_BF16S ? 2 : 4); }
 
 // ---------------------------------------------------------------------------
+// Source-indexed storage.  Population p of cell x is kept where the cell it
+// streams from wrote it: slot (block of x - c_p, p, cell of x - c_p) of the
+// block-major rows [block][p][cell].  A collide-stream sweep therefore reads
+// its cells' populations from its own and its neighbours' rows and writes
+// only its own rows, whole rows per wave.  Two kinds of population have no
+// upstream same-level cell:
+//   - the source lies outside the fluid (domain face or solid block): the
+//     population is the bounce-back of the cell's own outgoing population in
+//     the opposite direction, and is kept in that otherwise unused slot
+//     (x, opposite(p));
+//   - the source lies in a region covered only by a coarser block (N_SKIP):
+//     it is kept in the block's halo record, one per block with an N_SKIP
+//     link, at entry halo_index(p, cell).
+// The values are exactly those of a two-buffer push scheme; only where they
+// live differs.
+template <typename Lt>
+struct HaloIndex {
+    int16_t idx[Lt::Q][Lt::MB];
+    int n;
+    constexpr HaloIndex() : idx(), n(0) {
+        for (int p = 0; p < Lt::Q; p++)
+            for (int l = 0; l < Lt::MB; l++) {
+                const int sx = (l & 3) - Lt::cx(p), sy = ((l >> 2) & 3) - Lt::cy(p), sz = (l >> 4) - Lt::cz(p);
+                const bool inside = sx >= 0 && sx < 4 && sy >= 0 && sy < 4 && sz >= 0 && sz < 4;
+                idx[p][l] = inside ? int16_t(-1) : int16_t(n++);
+            }
+    }
+};
+template <typename Lt> constexpr HaloIndex<Lt> kHalo{};
+inline int halo_entries(int q) {
+    return q == 9 ? kHalo<Lat<9>>.n : (q == 19 ? kHalo<Lat<19>>.n : kHalo<Lat<27>>.n);
+}
+
+// ---------------------------------------------------------------------------
 // Device view of the forest.  Block metadata is structure-of-arrays: entry p
 // of block B lives at [p * cap + B] (the paper's kappa + p N_blocks layout);
-// distributions at [q * capc + B * Mb + l].
+// distribution rows are block-major, [B][q][l], followed by the halo records.
 struct DevMesh {
     int32_t cap;
     int64_t capc;
     int32_t lmax;
+    int64_t halo_base;  // first halo slot in a distribution buffer (= cap * Q * Mb)
+    int32_t nh;         // slots per halo record
+    int32_t *hid;       // halo record of each block, -1 if it has no N_SKIP link
+    int32_t *parent;    // parent block, -1 on the root level
+    int8_t *fresh;      // 1 for blocks created by the adaptation in progress
     int32_t *nbr, *nbrc, *X;
     int8_t *level, *status, *tag, *ldes, *viol;
     uint8_t *bflag;

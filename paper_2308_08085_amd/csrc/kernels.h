@@ -43,6 +43,7 @@ struct Ctx {
     int32_t *cnt;        // [cap]
     int32_t *off;        // [cap]
     double *crit;        // [cap]
+    double *U;           // [3][cap * Mb] FP64 cell velocities for the criterion
     double *part4;       // [cap * 4]
     uint8_t *solid;      // [nroot]
     int32_t *solid_list; // [nroot]
@@ -58,10 +59,15 @@ void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, cons
                            const BCParams &bc);
 // mode 0: ghost cells of children with an N_SKIP link; 1: every cell of every child
 void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells);
+// after new children (parents in `list`) were interpolated: the populations of
+// existing same-level neighbour cells that now stream from the new blocks
+void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const LevelParams &lp);
 // mode 0: interface parent cells; 1: every parent cell (non-refined entries are skipped)
 void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells);
 void launch_fill_rest(const Ctx &c);
-void launch_set_rho_u_root(const Ctx &c, const double *rho_u_dev, int cell0, int ncells);
+// initial condition on root blocks [b0, b1) from rho_u_dev[((B - b0) Mb + l) 4]
+void launch_set_rho_u_root(const Ctx &c, const double *rho_u_dev, int b0, int b1);
+void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp);
 void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp);
 void launch_block_f(const Ctx &c, int set, int b0, int b1, double *stage, const LevelParams &lp);
 void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, void *stage, const LevelParams &lp);
@@ -75,7 +81,7 @@ void launch_tag_distance(const Ctx &c, double d_spec, int freeze);
 void launch_effective_tags(const Ctx &c);
 // adaptation after the counts are known on the host
 void launch_adapt_assign(const Ctx &c, int n_ref);                 // S2 + S3
-void launch_adapt_build(const Ctx &c, int n_ref, const LevelParams &lp);  // S4 .. S7
+void launch_adapt_build(const Ctx &c, int n_ref);                 // S4 .. S7 (statuses)
 void launch_connectivity(const Ctx &c, int id_bound);             // S8 + masks + interface lists
 void launch_out_count(const Ctx &c);  // per-block output counts + exclusive offsets, n_out
 

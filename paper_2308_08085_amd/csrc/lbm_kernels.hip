@@ -1,13 +1,35 @@
 // lbm_kernels.hip -- lattice Boltzmann kernels of the AMR-LBM library for
-// gfx950: fused BGK collide + push stream per level sweep, coarse-to-fine
-// linear interpolation, fine-to-coarse averaging, the vorticity criterion and
-// field gathers.  Arithmetic is written in the "shifted" variables g = f - w
-// for every storage format (FP64 storage computes in FP64, the rest in FP32).
+// gfx950: fused BGK collide + stream per level sweep, coarse-to-fine linear
+// interpolation, fine-to-coarse averaging, the vorticity criterion and field
+// gathers.  Arithmetic is written in the shifted variables g = f - w for every
+// storage format (FP64 storage computes in FP64, the rest in FP32).
+//
+// Distributions are stored source-indexed in block-major rows (see common.h):
+// every kernel finds population p of a cell with entry_slot().
 #include "kernels.h"
 
 namespace amr {
 
-#define HIP_LAUNCH_CHECK() (void)hipGetLastError()
+template <typename Lt>
+__device__ __forceinline__ int64_t mslot(int B, int p, int l) {
+    return ((int64_t)B * Lt::Q + p) * Lt::MB + l;
+}
+
+template <typename Lt>
+__device__ __forceinline__ int dir_region(int p) {
+    return offset_slot(Lt::cx(p), Lt::cy(p), Lt::cz(p)) - (Lt::D == 2 ? 9 : 0);
+}
+
+// slot holding population p of cell l of block B (h = its halo record); link
+// is the block's link table in region-slot order
+template <typename Lt>
+__device__ __forceinline__ int64_t entry_slot(const DevMesh &m, const int32_t *link, int B, int h, int p, int l) {
+    const int sx = (l & 3) - Lt::cx(p), sy = ((l >> 2) & 3) - Lt::cy(p), sz = (l >> 4) - Lt::cz(p);
+    const int32_t code = link[region_of<Lt>(sx, sy, sz)];
+    if (code >= 0 && code < m.cap) return mslot<Lt>(code, p, (sx & 3) + 4 * (sy & 3) + 16 * (sz & 3));
+    if (code == kNSkip && h >= 0) return m.halo_base + (int64_t)h * m.nh + kHalo<Lt>.idx[p][l];
+    return mslot<Lt>(B, Lt::opp(p), l);
+}
 
 template <typename Lt, typename R>
 __device__ inline void moments_g(const R *g, R &drho, R &ux, R &uy, R &uz) {
@@ -36,28 +58,66 @@ __device__ inline R geq(int p, R drho, R ux, R uy, R uz, R uu) {
 }
 
 template <typename Lt, typename ST>
-__device__ inline void load_g(const typename ST::T *__restrict__ f, int64_t capc, int64_t cell, typename ST::R *g) {
+__device__ __forceinline__ typename ST::R load_g(const typename ST::T *f, int64_t slot, int p) {
     using R = typename ST::R;
-#pragma unroll
-    for (int p = 0; p < Lt::Q; p++) {
-        const R v = ST::ld(f + p * capc + cell);
-        g[p] = ST::shift ? v : v - R(Lt::w(p));
-    }
+    const R v = ST::ld(f + slot);
+    return ST::shift ? v : v - R(Lt::w(p));
 }
 
 template <typename Lt, typename ST>
-__device__ inline void store_g(typename ST::T *__restrict__ f, int64_t capc, int64_t cell, int p, typename ST::R g) {
+__device__ __forceinline__ void store_g(typename ST::T *f, int64_t slot, int p, typename ST::R g) {
     using R = typename ST::R;
-    ST::st(f + p * capc + cell, ST::shift ? g : g + R(Lt::w(p)));
+    ST::st(f + slot, ST::shift ? g : g + R(Lt::w(p)));
+}
+
+// gather / scatter all populations of one cell
+template <typename Lt, typename ST>
+__device__ __forceinline__ void gather_cell(const DevMesh &m, const int32_t *link, int B, int h, int l,
+                                            const typename ST::T *f, typename ST::R *g) {
+#pragma unroll
+    for (int p = 0; p < Lt::Q; p++) g[p] = load_g<Lt, ST>(f, entry_slot<Lt>(m, link, B, h, p, l), p);
+}
+
+template <typename Lt, typename ST>
+__device__ __forceinline__ void scatter_cell(const DevMesh &m, const int32_t *link, int B, int h, int l,
+                                             typename ST::T *f, const typename ST::R *g) {
+#pragma unroll
+    for (int p = 0; p < Lt::Q; p++) store_g<Lt, ST>(f, entry_slot<Lt>(m, link, B, h, p, l), p, g[p]);
+}
+
+// Per-workgroup staging of NBLK block descriptors; links by region slot.
+template <typename Lt, int NBLK>
+struct BlockStage {
+    static constexpr int NS = Lt::D == 2 ? 9 : 27;
+    int32_t link[NBLK][NS];
+    int32_t id[NBLK];
+    int32_t hid[NBLK];
+    uint8_t flag[NBLK];
+};
+
+// st.id[] (-1 = none) must be written and synchronised before the call
+template <typename Lt, int NBLK>
+__device__ void stage_blocks(const DevMesh &m, BlockStage<Lt, NBLK> &st) {
+    for (int e = threadIdx.x; e < NBLK * Lt::NB; e += blockDim.x) {
+        const int s = e / Lt::NB, p = e - s * Lt::NB;
+        const int B = st.id[s];
+        st.link[s][dir_region<Lt>(p)] = B >= 0 ? m.nbr[(int64_t)p * m.cap + B] : 0;
+        if (p == 0) {
+            st.hid[s] = B >= 0 ? m.hid[B] : -1;
+            st.flag[s] = B >= 0 ? m.bflag[B] : 0;
+        }
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// Fused collide + push stream of one level (Secs. "Streaming", "Collision").
-// One 4^d block per 64-lane group (3-D: one block per wave; 2-D: four blocks
-// per wave); each workgroup stages the link tables of its blocks in LDS,
-// indexed by neighbour-offset slot.  Pushes that leave the fluid turn into the
-// boundary value in the opposite slot of the same cell; slots whose source is
-// an N_SKIP region keep the cell's own post-collision value.
+// Fused collide + stream of one level (Secs. "Streaming", "Collision").  One
+// 4^d block per 64-lane group (3-D: one block per wave; 2-D: four blocks per
+// wave).  Each cell gathers its populations, collides, and writes its
+// outgoing populations to its own slots; an outgoing population that would
+// leave the fluid is replaced there by its bounce-back.  A population arriving
+// from a region covered only by a coarser block keeps the cell's own
+// post-collision value (halo record).
 template <int Q, int S>
 __global__ __launch_bounds__(256) void k_collide_stream(const int32_t *__restrict__ list, int n, DevMesh m,
                                                         const typename Store<S>::T *__restrict__ src,
@@ -66,37 +126,23 @@ __global__ __launch_bounds__(256) void k_collide_stream(const int32_t *__restric
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
-    constexpr int MB = Lt::MB, BPW = 256 / MB, NS = Lt::D == 2 ? 9 : 27;
-    __shared__ int32_t s_link[BPW][NS];
-    __shared__ int32_t s_id[BPW];
-    __shared__ uint8_t s_flag[BPW];
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int base = wg * BPW;
-    for (int e = threadIdx.x; e < BPW * Lt::NB; e += 256) {
-        const int s = e / Lt::NB, p = e - s * Lt::NB;
-        const int idx = base + s;
-        int32_t v = 0;
-        if (idx < n) {
-            const int B = list[idx];
-            v = m.nbr[(int64_t)p * m.cap + B];
-            if (p == 0) {
-                s_id[s] = B;
-                s_flag[s] = m.bflag[B];
-            }
-        }
-        s_link[s][offset_slot(Lt::cx(p), Lt::cy(p), Lt::cz(p)) - (Lt::D == 2 ? 9 : 0)] = v;
-    }
+    if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
     __syncthreads();
+    stage_blocks<Lt, BPW>(m, st);
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
-    if (base + s >= n) return;
-    const int B = s_id[s];
-    const uint8_t flag = s_flag[s];
+    const int B = st.id[s];
+    if (B < 0) return;
+    const uint8_t flag = st.flag[s];
+    const int h = st.hid[s];
+    const int32_t *link = st.link[s];
     const int i = l & 3, j = (l >> 2) & 3, k = l >> 4;
-    const int64_t cell = (int64_t)B * MB + l;
-    const int64_t capc = m.capc;
 
     R g[Q];
-    load_g<Lt, ST>(src, capc, cell, g);
+    gather_cell<Lt, ST>(m, link, B, h, l, src, g);
     R drho, ux, uy, uz;
     moments_g<Lt, R>(g, drho, ux, uy, uz);
     const R uu = ux * ux + uy * uy + uz * uz;
@@ -105,43 +151,36 @@ __global__ __launch_bounds__(256) void k_collide_stream(const int32_t *__restric
     for (int p = 0; p < Q; p++) g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
 
 #pragma unroll
-    for (int p = 0; p < Q; p++) {
-        const int tx = i + Lt::cx(p), ty = j + Lt::cy(p), tz = k + Lt::cz(p);
-        const int rx = tx < 0 ? -1 : (tx > 3 ? 1 : 0);
-        const int ry = ty < 0 ? -1 : (ty > 3 ? 1 : 0);
-        const int rz = tz < 0 ? -1 : (tz > 3 ? 1 : 0);
-        const int32_t code = s_link[s][offset_slot(rx, ry, rz) - (Lt::D == 2 ? 9 : 0)];
-        if (code >= 0) {
-            if (code >= m.cap) continue;  // never taken for a consistent forest
-            const int lt = (tx & 3) + 4 * (ty & 3) + 16 * (tz & 3);
-            store_g<Lt, ST>(dst, capc, (int64_t)code * MB + lt, p, g[p]);
-        } else if ((flag & BF_BOUNDARY) && code != kNSkip) {
-            R val;
-            if (code == kSolid) {
-                val = g[p];
-            } else {
-                const int face = -3 - code;
-                const R cx = R(Lt::cx(p)), cy = R(Lt::cy(p)), cz = R(Lt::cz(p));
-                if (bc.kind[face] == AMR_FACE_VELOCITY) {
-                    const R cuw = cx * R(bc.u[face][0]) + cy * R(bc.u[face][1]) + cz * R(bc.u[face][2]);
-                    val = g[p] - R(6) * R(Lt::w(p)) * cuw;
+    for (int q = 0; q < Q; q++) {
+        if (flag & BF_BOUNDARY) {
+            const int32_t code = link[region_of<Lt>(i + Lt::cx(q), j + Lt::cy(q), k + Lt::cz(q))];
+            if (code < 0 && code != kNSkip) {
+                R val;
+                if (code == kSolid) {
+                    val = g[q];
                 } else {
-                    const R cu = cx * ux + cy * uy + cz * uz;
-                    val = -g[p] + R(2) * R(Lt::w(p)) * (R(4.5) * cu * cu - R(1.5) * uu);
+                    const int face = -3 - code;
+                    const R cx = R(Lt::cx(q)), cy = R(Lt::cy(q)), cz = R(Lt::cz(q));
+                    if (bc.kind[face] == AMR_FACE_VELOCITY) {
+                        const R cuw = cx * R(bc.u[face][0]) + cy * R(bc.u[face][1]) + cz * R(bc.u[face][2]);
+                        val = g[q] - R(6) * R(Lt::w(q)) * cuw;
+                    } else {
+                        const R cu = cx * ux + cy * uy + cz * uz;
+                        val = -g[q] + R(2) * R(Lt::w(q)) * (R(4.5) * cu * cu - R(1.5) * uu);
+                    }
                 }
+                // the slot now holds population opposite(q) of this cell
+                store_g<Lt, ST>(dst, mslot<Lt>(B, q, l), Lt::opp(q), val);
+                continue;
             }
-            store_g<Lt, ST>(dst, capc, cell, Lt::opp(p), val);
         }
+        store_g<Lt, ST>(dst, mslot<Lt>(B, q, l), q, g[q]);
     }
-    if (flag & BF_NSKIP) {
+    if ((flag & BF_NSKIP) && h >= 0) {
 #pragma unroll
         for (int p = 1; p < Q; p++) {
-            const int sx = i - Lt::cx(p), sy = j - Lt::cy(p), sz = k - Lt::cz(p);
-            const int rx = sx < 0 ? -1 : (sx > 3 ? 1 : 0);
-            const int ry = sy < 0 ? -1 : (sy > 3 ? 1 : 0);
-            const int rz = sz < 0 ? -1 : (sz > 3 ? 1 : 0);
-            if (s_link[s][offset_slot(rx, ry, rz) - (Lt::D == 2 ? 9 : 0)] == kNSkip)
-                store_g<Lt, ST>(dst, capc, cell, p, g[p]);
+            if (link[region_of<Lt>(i - Lt::cx(p), j - Lt::cy(p), k - Lt::cz(p))] == kNSkip)
+                store_g<Lt, ST>(dst, m.halo_base + (int64_t)h * m.nh + kHalo<Lt>.idx[p][l], p, g[p]);
         }
     }
 }
@@ -181,6 +220,7 @@ __global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list
     constexpr int MB = Lt::MB, NC = Lt::NC;
     __shared__ R s_g[Q][MB];
     __shared__ uint64_t s_gm[NC];
+    __shared__ BlockStage<Lt, NC + 1> st;  // entry NC = the parent
     if ((int)blockIdx.x >= n) return;
     const int P = list[blockIdx.x];
     const int L = m.level[P];
@@ -190,10 +230,13 @@ __global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list
     T *dst = lp.par[L + 1] ? f1 : f0;
     const R r = R(lp.r_cf[L]);
     const int t = threadIdx.x;
+    if (t <= NC) st.id[t] = t < NC ? first + t : P;
     if (t < NC) s_gm[t] = all_cells ? ~0ull : m.gmask[first + t];
+    __syncthreads();
+    stage_blocks<Lt, NC + 1>(m, st);
     if (t < MB) {
         R g[Q];
-        load_g<Lt, ST>(src, m.capc, (int64_t)P * MB + t, g);
+        gather_cell<Lt, ST>(m, st.link[NC], P, st.hid[NC], t, src, g);
         R drho, ux, uy, uz;
         moments_g<Lt, R>(g, drho, ux, uy, uz);
         const R uu = ux * ux + uy * uy + uz * uz;
@@ -211,7 +254,8 @@ __global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list
         const int I = lf & 3, J = (lf >> 2) & 3, K = lf >> 4;
         const R x = R(-0.25) + R(0.5) * R(I), y = R(-0.25) + R(0.5) * R(J), z = R(-0.25) + R(0.5) * R(K);
         const int m0 = 2 * cx + 4 * (2 * cy) + 16 * (2 * cz);
-        const int64_t cell = (int64_t)(first + c) * MB + lf;
+        const int32_t *link = st.link[c];
+        const int hc = st.hid[c];
 #pragma unroll
         for (int p = 0; p < Q; p++) {
             R v;
@@ -223,9 +267,107 @@ __global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list
                 for (int nn = 0; nn < 8; nn++) F[nn] = s_g[p][m0 + (nn & 1) + 4 * ((nn >> 1) & 1) + 16 * (nn >> 2)];
                 v = lin3<R>(F, x, y, z);
             }
-            store_g<Lt, ST>(dst, m.capc, cell, p, v);
+            store_g<Lt, ST>(dst, entry_slot<Lt>(m, link, first + c, hc, p, lf), p, v);
         }
     }
+}
+
+// Refresh after refinement.  A cell x of an existing block N next to a new
+// same-level block C now receives the populations that stream from C's cells;
+// they are stored in C's rows, which the interpolation of C's own cells does
+// not write.  Their values are those x already had: the ghost interpolation
+// from N's parent (x was adjacent to the region C now covers, which was
+// covered only by a coarser block).  One workgroup per refined parent.
+template <int Q, int S>
+__global__ __launch_bounds__(256) void k_refresh_neighbours(const int32_t *__restrict__ list, int n, DevMesh m,
+                                                            typename Store<S>::T *f0, typename Store<S>::T *f1,
+                                                            LevelParams lp) {
+    using Lt = Lat<Q>;
+    using ST = Store<S>;
+    using R = typename ST::R;
+    using T = typename ST::T;
+    constexpr int MB = Lt::MB, NC = Lt::NC, NS = Lt::D == 2 ? 9 : 27;
+    __shared__ R s_g[Q][MB];
+    __shared__ BlockStage<Lt, NC + 1> st;  // the new children, then the neighbour's parent
+    __shared__ int s_nb[NC][NS];           // existing same-level neighbour per child and region, -1 none
+    if ((int)blockIdx.x >= n) return;
+    const int P = list[blockIdx.x];
+    const int L = m.level[P];
+    const int first = m.nbrc[P];
+    if (first < 0 || first > m.cap - NC || L + 1 >= m.lmax) return;
+    const T *psrc = lp.par[L] ? f1 : f0;
+    T *dst = lp.par[L + 1] ? f1 : f0;
+    const R r = R(lp.r_cf[L]);
+    const int t = threadIdx.x;
+    if (t < NC) st.id[t] = first + t;
+    if (t == NC) st.id[NC] = -1;
+    __syncthreads();
+    stage_blocks<Lt, NC + 1>(m, st);
+    for (int e = t; e < NC * NS; e += blockDim.x) {
+        const int c = e / NS, rg = e - c * NS;
+        const int N = st.link[c][rg];
+        s_nb[c][rg] = (rg != kCenterSlot<Lt> && N >= 0 && N < m.cap && !m.fresh[N] && m.parent[N] >= 0) ? N : -1;
+    }
+    __syncthreads();
+    for (int c = 0; c < NC; c++) {
+        for (int rg = 0; rg < NS; rg++) {
+            const int N = s_nb[c][rg];  // uniform over the workgroup
+            if (N < 0) continue;
+            const int PN = m.parent[N];
+            const int cN = N - m.nbrc[PN];
+            if (t == 0) st.id[NC] = PN;
+            __syncthreads();
+            for (int e = t; e < Lt::NB; e += blockDim.x)
+                st.link[NC][dir_region<Lt>(e)] = m.nbr[(int64_t)e * m.cap + PN];
+            if (t == 0) st.hid[NC] = m.hid[PN];
+            __syncthreads();
+            if (t < MB) {
+                R g[Q];
+                gather_cell<Lt, ST>(m, st.link[NC], PN, st.hid[NC], t, psrc, g);
+                R drho, ux, uy, uz;
+                moments_g<Lt, R>(g, drho, ux, uy, uz);
+                const R uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+                for (int p = 0; p < Q; p++) {
+                    const R ge = geq<Lt, R>(p, drho, ux, uy, uz, uu);
+                    s_g[p][t] = ge + r * (g[p] - ge);
+                }
+            }
+            __syncthreads();
+            if (t < MB) {
+                const int si = t & 3, sj = (t >> 2) & 3, sk = t >> 4;
+                const int cx = cN & 1, cy = (cN >> 1) & 1, cz = (cN >> 2) & 1;
+                const int m0 = 2 * cx + 4 * (2 * cy) + 16 * (2 * cz);
+#pragma unroll
+                for (int p = 1; p < Q; p++) {
+                    const int tx = si + Lt::cx(p), ty = sj + Lt::cy(p), tz = sk + Lt::cz(p);
+                    if (region_of<Lt>(tx, ty, tz) != rg) continue;
+                    // cell x of N, and its position in the unit square/cube of N's quadrant
+                    const int I = tx & 3, J = ty & 3, K = tz & 3;
+                    const R x = R(-0.25) + R(0.5) * R(I), y = R(-0.25) + R(0.5) * R(J), z = R(-0.25) + R(0.5) * R(K);
+                    R v;
+                    if (Lt::D == 2) {
+                        v = lin2<R>(s_g[p][m0], s_g[p][m0 + 1], s_g[p][m0 + 4], s_g[p][m0 + 5], x, y);
+                    } else {
+                        R F[8];
+#pragma unroll
+                        for (int nn = 0; nn < 8; nn++) F[nn] = s_g[p][m0 + (nn & 1) + 4 * ((nn >> 1) & 1) + 16 * (nn >> 2)];
+                        v = lin3<R>(F, x, y, z);
+                    }
+                    store_g<Lt, ST>(dst, mslot<Lt>(first + c, p, t), p, v);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_clear_fresh(const int32_t *__restrict__ list, int n, DevMesh m, int nc) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * nc) return;
+    const int P = list[e / nc];
+    const int first = m.nbrc[P];
+    if (first >= 0 && first + e % nc < m.cap) m.fresh[first + e % nc] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -242,136 +384,186 @@ __global__ __launch_bounds__(64) void k_average(const int32_t *__restrict__ list
     using R = typename ST::R;
     using T = typename ST::T;
     constexpr int MB = Lt::MB, NC = Lt::NC, PPW = 64 / MB;
+    __shared__ BlockStage<Lt, PPW * (NC + 1)> st;  // per parent: NC children, then the parent
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
-    const int idx = blockIdx.x * PPW + s;
-    if (idx >= n) return;
-    const int P = list[idx];
-    if (!is_refined(m.status[P])) return;
+    if ((int)threadIdx.x < PPW * (NC + 1)) {
+        const int ps = threadIdx.x / (NC + 1), c = threadIdx.x - ps * (NC + 1);
+        const int idx = blockIdx.x * PPW + ps;
+        int id = -1;
+        if (idx < n) {
+            const int P = list[idx];
+            const int c0 = m.nbrc[P];
+            const bool ok = is_refined(m.status[P]) && c0 >= 0 && c0 <= m.cap - NC && m.level[P] + 1 < m.lmax;
+            if (ok) id = c < NC ? c0 + c : P;
+        }
+        st.id[threadIdx.x] = id;
+    }
+    __syncthreads();
+    stage_blocks<Lt, PPW * (NC + 1)>(m, st);
+    const int sb = s * (NC + 1);
+    const int P = st.id[sb + NC];
+    if (P < 0) return;
     const int L = m.level[P];
-    const int c0 = m.nbrc[P];
-    if (c0 < 0 || c0 > m.cap - NC || L + 1 >= m.lmax) return;
     const int i = l & 3, j = (l >> 2) & 3, k = l >> 4;
-    const int child = c0 + (i >> 1) + 2 * (j >> 1) + 4 * (k >> 1);
+    const int c = (i >> 1) + 2 * (j >> 1) + 4 * (k >> 1);
+    const int child = st.id[sb + c];
     const int fb = 2 * (i & 1) + 8 * (j & 1) + 32 * (k & 1);
     if (!all_cells && !((m.imask[child] >> fb) & 1ull)) return;
     const T *src = lp.par[L + 1] ? f1 : f0;
     T *dst = lp.par[L] ? f1 : f0;
     const R r = R(lp.r_fc[L]);
-    R acc[Q];
+    // mean of the rescaled fine cells, sum_n [geq_n + r (g_n - geq_n)] / N_c,
+    // evaluated as ((1 - r) sum_n geq_n + r sum_n g_n) / N_c so that only the
+    // populations' sum and each fine cell's moments stay live
+    R acc[Q], se[Q];
 #pragma unroll
-    for (int p = 0; p < Q; p++) acc[p] = R(0);
-#pragma unroll
+    for (int p = 0; p < Q; p++) {
+        acc[p] = R(0);
+        se[p] = R(0);
+    }
+    const int32_t *clink = st.link[sb + c];
+    const int ch = st.hid[sb + c];
+#pragma unroll 1
     for (int nn = 0; nn < NC; nn++) {
         const int lf = fb + (nn & 1) + 4 * ((nn >> 1) & 1) + 16 * (nn >> 2);
-        R g[Q];
-        load_g<Lt, ST>(src, m.capc, (int64_t)child * MB + lf, g);
-        R drho, ux, uy, uz;
-        moments_g<Lt, R>(g, drho, ux, uy, uz);
-        const R uu = ux * ux + uy * uy + uz * uz;
+        R d = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
         for (int p = 0; p < Q; p++) {
-            const R ge = geq<Lt, R>(p, drho, ux, uy, uz, uu);
-            acc[p] += ge + r * (g[p] - ge);
+            const R gv = load_g<Lt, ST>(src, entry_slot<Lt>(m, clink, child, ch, p, lf), p);
+            acc[p] += gv;
+            d += gv;
+            if (Lt::cx(p) > 0) jx += gv; else if (Lt::cx(p) < 0) jx -= gv;
+            if (Lt::cy(p) > 0) jy += gv; else if (Lt::cy(p) < 0) jy -= gv;
+            if (Lt::cz(p) > 0) jz += gv; else if (Lt::cz(p) < 0) jz -= gv;
         }
-    }
-    const int64_t cell = (int64_t)P * MB + l;
+        const R rho = R(1) + d;
+        const R ux = jx / rho, uy = jy / rho, uz = jz / rho;
+        const R uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
-    for (int p = 0; p < Q; p++) store_g<Lt, ST>(dst, m.capc, cell, p, acc[p] / R(NC));
+        for (int p = 0; p < Q; p++) se[p] += geq<Lt, R>(p, d, ux, uy, uz, uu);
+    }
+    const int32_t *plink = st.link[sb + NC];
+    const int ph = st.hid[sb + NC];
+#pragma unroll
+    for (int p = 0; p < Q; p++) {
+        const R v = ((R(1) - r) * se[p] + r * acc[p]) / R(NC);
+        store_g<Lt, ST>(dst, entry_slot<Lt>(m, plink, P, ph, p, l), p, v);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// initial states
+// initial states: every slot at rest (g = 0, f = w)
 template <int Q, int S>
-__global__ void k_fill_rest(DevMesh m, typename Store<S>::T *f0, typename Store<S>::T *f1) {
-    using Lt = Lat<Q>;
-    using ST = Store<S>;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m.capc) return;
-#pragma unroll
-    for (int p = 0; p < Q; p++) {
-        store_g<Lt, ST>(f0, m.capc, e, p, typename ST::R(0));
-        store_g<Lt, ST>(f1, m.capc, e, p, typename ST::R(0));
-    }
-}
-
-// f = feq(rho, u) on root cells, from (rho, ux, uy, uz) in (root block, cell) order
-template <int Q, int S>
-__global__ void k_set_rho_u(DevMesh m, typename Store<S>::T *f, const double *__restrict__ ru, int cell0, int ncells) {
+__global__ void k_fill_rest(DevMesh m, typename Store<S>::T *f0, typename Store<S>::T *f1, int64_t total) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
-    const int el = blockIdx.x * blockDim.x + threadIdx.x;
-    if (el >= ncells) return;
-    const int e = cell0 + el;
-    const int B = e / Lt::MB;
-    if (m.status[B] == ST_INACTIVE) return;
-    const double rho = ru[4 * el], ux = ru[4 * el + 1], uy = ru[4 * el + 2], uz = ru[4 * el + 3];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    R v = R(0);
+    if (!ST::shift && e < m.halo_base) {
+        const int p = (int)((e / Lt::MB) % Q);
+        v = R(Lt::w(p));
+    }
+    ST::st(f0 + e, v);
+    ST::st(f1 + e, v);
+}
+
+// Block-parallel kernels below run 256/Mb blocks per 256-thread workgroup
+// over a contiguous block-ID range [b0, b1).
+
+// f = feq(rho, u) of root cells from (rho, ux, uy, uz), ru[((B - b0) Mb + l) 4]
+template <int Q, int S>
+__global__ __launch_bounds__(256) void k_set_rho_u(DevMesh m, typename Store<S>::T *f, const double *__restrict__ ru,
+                                                   int b0, int b1) {
+    using Lt = Lat<Q>;
+    using ST = Store<S>;
+    using R = typename ST::R;
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
+    if ((int)threadIdx.x < BPW) {
+        const int B = b0 + blockIdx.x * BPW + threadIdx.x;
+        st.id[threadIdx.x] = (B < b1 && m.status[B] != ST_INACTIVE) ? B : -1;
+    }
+    __syncthreads();
+    stage_blocks<Lt, BPW>(m, st);
+    const int s = threadIdx.x / MB, l = threadIdx.x % MB;
+    const int B = st.id[s];
+    if (B < 0) return;
+    const double *v = ru + ((int64_t)(B - b0) * MB + l) * 4;
+    const double rho = v[0], ux = v[1], uy = v[2], uz = v[3];
     const double uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
     for (int p = 0; p < Q; p++) {
         const double cu = Lt::cx(p) * ux + Lt::cy(p) * uy + Lt::cz(p) * uz;
-        if (ST::shift) {
-            const double gv = Lt::w(p) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-            ST::st(f + p * m.capc + e, R(gv));
-        } else {
-            const double fv = Lt::w(p) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-            ST::st(f + p * m.capc + e, R(fv));
-        }
+        const double val = ST::shift ? Lt::w(p) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu))
+                                     : Lt::w(p) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        ST::st(f + entry_slot<Lt>(m, st.link[s], B, st.hid[s], p, l), R(val));
     }
 }
 
 // ---------------------------------------------------------------------------
-// Vorticity criterion, FP64 (Sec. "Adaptive Mesh Refinement" of the solver):
-// central differences over same-level neighbour cells, one-sided where a
-// neighbour is missing, scaled to root-cell units; block maximum per leaf and
-// the global maximum (atomic max on the bit pattern of a non-negative double).
+// Vorticity criterion, FP64 (Sec. "Adaptive Mesh Refinement" of the solver).
+// First the FP64 velocity of every cell of a level, then central differences
+// over same-level neighbour cells (one-sided where a neighbour is missing),
+// scaled to root-cell units; block maximum per leaf and the global maximum
+// (atomic max on the bit pattern of a non-negative double).
 template <typename Lt, typename ST>
-__device__ inline void velocity_f64(const typename ST::T *__restrict__ f, int64_t capc, int64_t cell, double *u) {
-    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+__device__ inline void cell_f64(const DevMesh &m, const int32_t *link, int B, int h, int l,
+                                const typename ST::T *f, double *fv) {
 #pragma unroll
-    for (int p = 0; p < Lt::Q; p++) {
-        const double v = double(ST::ld(f + p * capc + cell)) + (ST::shift ? Lt::w(p) : 0.0);
-        rho += v;
-        j[0] += v * Lt::cx(p);
-        j[1] += v * Lt::cy(p);
-        j[2] += v * Lt::cz(p);
-    }
-    u[0] = j[0] / rho;
-    u[1] = j[1] / rho;
-    u[2] = j[2] / rho;
+    for (int p = 0; p < Lt::Q; p++)
+        fv[p] = double(ST::ld(f + entry_slot<Lt>(m, link, B, h, p, l))) + (ST::shift ? Lt::w(p) : 0.0);
 }
 
 template <int Q, int S>
-__global__ __launch_bounds__(256) void k_vorticity(const int32_t *__restrict__ list, int n, DevMesh m,
-                                                   const typename Store<S>::T *__restrict__ f, double scale,
-                                                   double *crit, unsigned long long *wmax_bits) {
+__global__ __launch_bounds__(256) void k_velocity(const int32_t *__restrict__ list, int n, DevMesh m,
+                                                  const typename Store<S>::T *__restrict__ f, double *U) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
-    constexpr int MB = Lt::MB, BPW = 256 / MB, NS = Lt::D == 2 ? 9 : 27;
-    __shared__ int32_t s_link[BPW][NS];
-    __shared__ int32_t s_id[BPW];
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
     const int base = blockIdx.x * BPW;
-    for (int e = threadIdx.x; e < BPW * Lt::NB; e += 256) {
-        const int s = e / Lt::NB, p = e - s * Lt::NB;
-        const int idx = base + s;
-        int32_t v = 0;
-        if (idx < n) {
-            const int B = list[idx];
-            v = m.nbr[(int64_t)p * m.cap + B];
-            if (p == 0) s_id[s] = B;
-        }
-        s_link[s][offset_slot(Lt::cx(p), Lt::cy(p), Lt::cz(p)) - (Lt::D == 2 ? 9 : 0)] = v;
-    }
+    if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
     __syncthreads();
+    stage_blocks<Lt, BPW>(m, st);
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
-    const bool valid = base + s < n;
-    const int B = valid ? s_id[s] : 0;
-    const bool leaf = valid && m.status[B] == ST_UNREF;
+    const int B = st.id[s];
+    if (B < 0) return;
+    double fv[Q];
+    cell_f64<Lt, ST>(m, st.link[s], B, st.hid[s], l, f, fv);
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < Q; p++) {
+        rho += fv[p];
+        j[0] += fv[p] * Lt::cx(p);
+        j[1] += fv[p] * Lt::cy(p);
+        j[2] += fv[p] * Lt::cz(p);
+    }
+    const int64_t cell = (int64_t)B * MB + l;
+    for (int a = 0; a < 3; a++) U[a * m.capc + cell] = j[a] / rho;
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_vorticity(const int32_t *__restrict__ list, int n, DevMesh m,
+                                                   const double *__restrict__ U, double scale, double *crit,
+                                                   unsigned long long *wmax_bits) {
+    using Lt = Lat<Q>;
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
+    const int base = blockIdx.x * BPW;
+    if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
+    __syncthreads();
+    stage_blocks<Lt, BPW>(m, st);
+    const int s = threadIdx.x / MB, l = threadIdx.x % MB;
+    const int B = st.id[s];
+    const bool leaf = B >= 0 && m.status[B] == ST_UNREF;
     double w = 0.0;
     if (leaf) {
         const int ci[3] = {l & 3, (l >> 2) & 3, l >> 4};
+        const int64_t cell = (int64_t)B * MB + l;
         double u0[3];
-        velocity_f64<Lt, ST>(f, m.capc, (int64_t)B * MB + l, u0);
+        for (int b = 0; b < 3; b++) u0[b] = U[b * m.capc + cell];
         double gr[3][3];
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) gr[a][b] = 0.0;
@@ -381,14 +573,12 @@ __global__ __launch_bounds__(256) void k_vorticity(const int32_t *__restrict__ l
             for (int sg = 0; sg < 2; sg++) {
                 int t[3] = {ci[0], ci[1], ci[2]};
                 t[a] += sg == 0 ? 1 : -1;
-                const int rx = t[0] < 0 ? -1 : (t[0] > 3 ? 1 : 0);
-                const int ry = t[1] < 0 ? -1 : (t[1] > 3 ? 1 : 0);
-                const int rz = t[2] < 0 ? -1 : (t[2] > 3 ? 1 : 0);
-                const int32_t code = s_link[s][offset_slot(rx, ry, rz) - (Lt::D == 2 ? 9 : 0)];
+                const int32_t code = st.link[s][region_of<Lt>(t[0], t[1], t[2])];
                 if (code < 0 || code >= m.cap) continue;
-                const int lt = (t[0] & 3) + 4 * (t[1] & 3) + 16 * (t[2] & 3);
-                if (sg == 0) { velocity_f64<Lt, ST>(f, m.capc, (int64_t)code * MB + lt, up); hp = true; }
-                else { velocity_f64<Lt, ST>(f, m.capc, (int64_t)code * MB + lt, um); hm = true; }
+                const int64_t nc = (int64_t)code * MB + (t[0] & 3) + 4 * (t[1] & 3) + 16 * (t[2] & 3);
+                double *dstv = sg == 0 ? up : um;
+                for (int b = 0; b < 3; b++) dstv[b] = U[b * m.capc + nc];
+                if (sg == 0) hp = true; else hm = true;
             }
             for (int b = 0; b < 3; b++) {
                 if (hp && hm) gr[a][b] = (up[b] - um[b]) / 2.0;
@@ -414,63 +604,81 @@ __global__ __launch_bounds__(256) void k_vorticity(const int32_t *__restrict__ l
 
 // ---------------------------------------------------------------------------
 // Gathers / scatters of unshifted FP64 data through the staging buffer.
+// Every cell of every active block, [B - b0][l][q]; inactive blocks read 0.
 template <int Q, int S>
-__global__ void k_block_f(DevMesh m, typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp, int set,
-                          int b0, int b1, double *stage) {
+__global__ __launch_bounds__(256) void k_block_f(DevMesh m, typename Store<S>::T *f0, typename Store<S>::T *f1,
+                                                 LevelParams lp, int set, int b0, int b1, double *stage) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ncell = (int64_t)(b1 - b0) * Lt::MB;
-    if (e >= ncell) return;
-    const int B = b0 + (int)(e / Lt::MB), l = (int)(e % Lt::MB);
-    const int L = m.level[B];
-    typename ST::T *f = lp.par[L] ? f1 : f0;
-    const int64_t cell = (int64_t)B * Lt::MB + l;
-    double *row = stage + e * Q;
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
+    if ((int)threadIdx.x < BPW) {
+        const int B = b0 + blockIdx.x * BPW + threadIdx.x;
+        st.id[threadIdx.x] = (B < b1 && m.status[B] != ST_INACTIVE) ? B : -1;
+    }
+    __syncthreads();
+    stage_blocks<Lt, BPW>(m, st);
+    const int s = threadIdx.x / MB, l = threadIdx.x % MB;
+    const int Braw = b0 + blockIdx.x * BPW + s;
+    if (Braw >= b1) return;
+    double *row = stage + ((int64_t)(Braw - b0) * MB + l) * Q;
+    const int B = st.id[s];
+    if (B < 0) {
+        if (!set)
+            for (int p = 0; p < Q; p++) row[p] = 0.0;
+        return;
+    }
+    typename ST::T *f = lp.par[m.level[B]] ? f1 : f0;
+    if (set) {
 #pragma unroll
-    for (int p = 0; p < Q; p++) {
-        if (set) {
-            const double v = row[p] - (ST::shift ? Lt::w(p) : 0.0);
-            ST::st(f + p * m.capc + cell, R(v));
-        } else {
-            row[p] = double(ST::ld(f + p * m.capc + cell)) + (ST::shift ? Lt::w(p) : 0.0);
-        }
+        for (int p = 0; p < Q; p++)
+            ST::st(f + entry_slot<Lt>(m, st.link[s], B, st.hid[s], p, l), R(row[p] - (ST::shift ? Lt::w(p) : 0.0)));
+    } else {
+        cell_f64<Lt, ST>(m, st.link[s], B, st.hid[s], l, f, row);
     }
 }
 
-// output cells: leaf, non-ghost cells in (block ID, cell) order; kind: 1 cells,
-// 2 rho/u, 3 f
+// output cells: leaf, non-ghost cells in (block ID, cell) order; kind: cells,
+// rho/u, or f
 template <int Q, int S>
-__global__ void k_out_gather(DevMesh m, typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
-                             int kind, int b0, int b1, const int32_t *__restrict__ off, int32_t off0, void *stage) {
+__global__ __launch_bounds__(256) void k_out_gather(DevMesh m, typename Store<S>::T *f0, typename Store<S>::T *f1,
+                                                    LevelParams lp, int kind, int b0, int b1,
+                                                    const int32_t *__restrict__ off, int32_t off0, void *stage) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
-    constexpr int MB = Lt::MB;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)(b1 - b0) * MB) return;
-    const int B = b0 + (int)(e / MB), l = (int)(e % MB);
-    if (m.status[B] != ST_UNREF) return;
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
+    if ((int)threadIdx.x < BPW) {
+        const int B = b0 + blockIdx.x * BPW + threadIdx.x;
+        st.id[threadIdx.x] = (B < b1 && m.status[B] == ST_UNREF) ? B : -1;
+    }
+    __syncthreads();
+    stage_blocks<Lt, BPW>(m, st);
+    const int s = threadIdx.x / MB, l = threadIdx.x % MB;
+    const int B = st.id[s];
+    if (B < 0) return;
     const uint64_t full = MB == 64 ? ~0ull : ((1ull << MB) - 1);
     const uint64_t outm = ~m.gmask[B] & full;
     if (!((outm >> l) & 1ull)) return;
     const int64_t pos = (int64_t)off[B] - off0 + __popcll(outm & ((1ull << l) - 1));
-    const int L = m.level[B];
-    const typename ST::T *f = lp.par[L] ? f1 : f0;
-    const int64_t cell = (int64_t)B * MB + l;
     if (kind == AMR_FIELD_CELLS) {
         int32_t *o = (int32_t *)stage + 2 * pos;
         o[0] = B;
         o[1] = l;
-    } else if (kind == AMR_FIELD_RHO_U) {
+        return;
+    }
+    const typename ST::T *f = lp.par[m.level[B]] ? f1 : f0;
+    double fv[Q];
+    cell_f64<Lt, ST>(m, st.link[s], B, st.hid[s], l, f, fv);
+    if (kind == AMR_FIELD_RHO_U) {
         double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int p = 0; p < Q; p++) {
-            const double v = double(ST::ld(f + p * m.capc + cell)) + (ST::shift ? Lt::w(p) : 0.0);
-            rho += v;
-            j[0] += v * Lt::cx(p);
-            j[1] += v * Lt::cy(p);
-            j[2] += v * Lt::cz(p);
+            rho += fv[p];
+            j[0] += fv[p] * Lt::cx(p);
+            j[1] += fv[p] * Lt::cy(p);
+            j[2] += fv[p] * Lt::cz(p);
         }
         double *o = (double *)stage + 4 * pos;
         o[0] = rho;
@@ -480,7 +688,7 @@ __global__ void k_out_gather(DevMesh m, typename Store<S>::T *f0, typename Store
     } else {
         double *o = (double *)stage + Q * pos;
 #pragma unroll
-        for (int p = 0; p < Q; p++) o[p] = double(ST::ld(f + p * m.capc + cell)) + (ST::shift ? Lt::w(p) : 0.0);
+        for (int p = 0; p < Q; p++) o[p] = fv[p];
     }
 }
 
@@ -491,23 +699,30 @@ __global__ __launch_bounds__(256) void k_mass_blocks(DevMesh m, typename Store<S
                                                      LevelParams lp, double *part4) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
-    constexpr int MB = Lt::MB;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int B = (int)(e / MB), l = (int)(e % MB);
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
+    if ((int)threadIdx.x < BPW) {
+        const int B = blockIdx.x * BPW + threadIdx.x;
+        st.id[threadIdx.x] = (B < m.cap && m.status[B] == ST_UNREF) ? B : -1;
+    }
+    __syncthreads();
+    stage_blocks<Lt, BPW>(m, st);
+    const int s = threadIdx.x / MB, l = threadIdx.x % MB;
+    const int Braw = blockIdx.x * BPW + s;
+    const int B = st.id[s];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    const bool inb = B < m.cap;
-    if (inb && m.status[B] == ST_UNREF && !((m.gmask[B] >> l) & 1ull)) {
+    if (B >= 0 && !((m.gmask[B] >> l) & 1ull)) {
         const int L = m.level[B];
         const typename ST::T *f = lp.par[L] ? f1 : f0;
-        const int64_t cell = (int64_t)B * MB + l;
+        double fv[Q];
+        cell_f64<Lt, ST>(m, st.link[s], B, st.hid[s], l, f, fv);
         double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int p = 0; p < Q; p++) {
-            const double x = double(ST::ld(f + p * m.capc + cell)) + (ST::shift ? Lt::w(p) : 0.0);
-            rho += x;
-            j[0] += x * Lt::cx(p);
-            j[1] += x * Lt::cy(p);
-            j[2] += x * Lt::cz(p);
+            rho += fv[p];
+            j[0] += fv[p] * Lt::cx(p);
+            j[1] += fv[p] * Lt::cy(p);
+            j[2] += fv[p] * Lt::cz(p);
         }
         const double vol = 1.0 / double(1 << (Lt::D * L));
         v[0] = vol * rho;
@@ -516,8 +731,8 @@ __global__ __launch_bounds__(256) void k_mass_blocks(DevMesh m, typename Store<S
 #pragma unroll
     for (int off = MB / 2; off > 0; off >>= 1)
         for (int a = 0; a < 4; a++) v[a] += __shfl_xor(v[a], off, 64);
-    if (inb && l == 0)
-        for (int a = 0; a < 4; a++) part4[(int64_t)B * 4 + a] = v[a];
+    if (Braw < m.cap && l == 0)
+        for (int a = 0; a < 4; a++) part4[(int64_t)Braw * 4 + a] = v[a];
 }
 
 __global__ __launch_bounds__(256) void k_mass_final(const double *part4, int cap, double *out) {
@@ -561,14 +776,17 @@ __global__ __launch_bounds__(256) void k_mass_final(const double *part4, int cap
 
 #define TPTR(Sc, p) ((typename Store<Sc>::T *)(p))
 
+static inline int grid_blocks(int64_t nblocks, int mb) {
+    const int bpw = 256 / mb;
+    return (int)((nblocks + bpw - 1) / bpw);
+}
+
 void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, const BCParams &bc) {
     if (n <= 0) return;
-    const int bpw = 256 / c.mb;
-    const int grid = (n + bpw - 1) / bpw;
     const int sp = lp.par[L];
     AMR_DISPATCH(c.q, c.storage,
-                 (k_collide_stream<Qc, Sc><<<grid, 256, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[sp]),
-                                                                       TPTR(Sc, c.f[1 - sp]), lp.omega[L], bc)));
+                 (k_collide_stream<Qc, Sc><<<grid_blocks(n, c.mb), 256, 0, c.stream>>>(
+                     list, n, c.m, TPTR(Sc, c.f[sp]), TPTR(Sc, c.f[1 - sp]), lp.omega[L], bc)));
 }
 
 void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {
@@ -577,6 +795,15 @@ void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &
     AMR_DISPATCH(c.q, c.storage,
                  (k_interp<Qc, Sc><<<n, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]),
                                                                  lp, all_cells)));
+}
+
+void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const LevelParams &lp) {
+    if (n <= 0) return;
+    const int threads = c.dim == 2 ? 64 : 256;
+    AMR_DISPATCH(c.q, c.storage,
+                 (k_refresh_neighbours<Qc, Sc><<<n, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]),
+                                                                             TPTR(Sc, c.f[1]), lp)));
+    k_clear_fresh<<<(n * c.nc + 255) / 256, 256, 0, c.stream>>>(list, n, c.m, c.nc);
 }
 
 void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {
@@ -589,52 +816,53 @@ void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams 
 }
 
 void launch_fill_rest(const Ctx &c) {
-    const int grid = (int)((c.m.capc + 255) / 256);
+    const int64_t total = c.m.halo_base + (int64_t)c.m.cap * c.m.nh;
+    const int grid = (int)((total + 255) / 256);
     AMR_DISPATCH(c.q, c.storage,
-                 (k_fill_rest<Qc, Sc><<<grid, 256, 0, c.stream>>>(c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]))));
+                 (k_fill_rest<Qc, Sc><<<grid, 256, 0, c.stream>>>(c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]), total)));
 }
 
-void launch_set_rho_u_root(const Ctx &c, const double *ru, int cell0, int ncells) {
-    if (ncells <= 0) return;
-    const int grid = (ncells + 255) / 256;
+void launch_set_rho_u_root(const Ctx &c, const double *ru, int b0, int b1) {
+    if (b1 <= b0) return;
     AMR_DISPATCH(c.q, c.storage,
-                 (k_set_rho_u<Qc, Sc><<<grid, 256, 0, c.stream>>>(c.m, TPTR(Sc, c.f[0]), ru, cell0, ncells)));
+                 (k_set_rho_u<Qc, Sc><<<grid_blocks(b1 - b0, c.mb), 256, 0, c.stream>>>(c.m, TPTR(Sc, c.f[0]), ru,
+                                                                                         b0, b1)));
 }
 
-void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp) {
+void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp) {
     if (n <= 0) return;
-    const int bpw = 256 / c.mb;
-    const int grid = (n + bpw - 1) / bpw;
-    const double scale = double(1 << L);
     AMR_DISPATCH(c.q, c.storage,
-                 (k_vorticity<Qc, Sc><<<grid, 256, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[lp.par[L]]), scale,
-                                                                  c.crit, &c.ctr->wmax_bits)));
+                 (k_velocity<Qc, Sc><<<grid_blocks(n, c.mb), 256, 0, c.stream>>>(list, n, c.m,
+                                                                                  TPTR(Sc, c.f[lp.par[L]]), c.U)));
+}
+
+void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &) {
+    if (n <= 0) return;
+    const double scale = double(1 << L);
+    const int grid = grid_blocks(n, c.mb);
+    if (c.q == 9) k_vorticity<9><<<grid, 256, 0, c.stream>>>(list, n, c.m, c.U, scale, c.crit, &c.ctr->wmax_bits);
+    else if (c.q == 19) k_vorticity<19><<<grid, 256, 0, c.stream>>>(list, n, c.m, c.U, scale, c.crit, &c.ctr->wmax_bits);
+    else k_vorticity<27><<<grid, 256, 0, c.stream>>>(list, n, c.m, c.U, scale, c.crit, &c.ctr->wmax_bits);
 }
 
 void launch_block_f(const Ctx &c, int set, int b0, int b1, double *stage, const LevelParams &lp) {
-    const int64_t n = (int64_t)(b1 - b0) * c.mb;
-    if (n <= 0) return;
-    const int grid = (int)((n + 255) / 256);
+    if (b1 <= b0) return;
     AMR_DISPATCH(c.q, c.storage,
-                 (k_block_f<Qc, Sc><<<grid, 256, 0, c.stream>>>(c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]), lp, set, b0,
-                                                                b1, stage)));
+                 (k_block_f<Qc, Sc><<<grid_blocks(b1 - b0, c.mb), 256, 0, c.stream>>>(
+                     c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]), lp, set, b0, b1, stage)));
 }
 
 void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, void *stage, const LevelParams &lp) {
-    const int64_t n = (int64_t)(b1 - b0) * c.mb;
-    if (n <= 0) return;
-    const int grid = (int)((n + 255) / 256);
+    if (b1 <= b0) return;
     AMR_DISPATCH(c.q, c.storage,
-                 (k_out_gather<Qc, Sc><<<grid, 256, 0, c.stream>>>(c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]), lp, kind,
-                                                                   b0, b1, c.off, off0, stage)));
+                 (k_out_gather<Qc, Sc><<<grid_blocks(b1 - b0, c.mb), 256, 0, c.stream>>>(
+                     c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]), lp, kind, b0, b1, c.off, off0, stage)));
 }
 
 void launch_mass(const Ctx &c, const LevelParams &lp) {
-    const int64_t n = (int64_t)c.m.cap * c.mb;
-    const int grid = (int)((n + 255) / 256);
     AMR_DISPATCH(c.q, c.storage,
-                 (k_mass_blocks<Qc, Sc><<<grid, 256, 0, c.stream>>>(c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]), lp,
-                                                                    c.part4)));
+                 (k_mass_blocks<Qc, Sc><<<grid_blocks(c.m.cap, c.mb), 256, 0, c.stream>>>(
+                     c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]), lp, c.part4)));
     k_mass_final<<<1, 256, 0, c.stream>>>(c.part4, c.m.cap, c.ctr->mass);
 }
 

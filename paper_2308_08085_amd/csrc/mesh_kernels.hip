@@ -204,6 +204,8 @@ __global__ void k_init_blocks(DevMesh m, RootParams rp, const uint8_t *solid, in
     m.gmask[B] = 0;
     m.imask[B] = 0;
     m.level[B] = 0;
+    m.parent[B] = -1;
+    m.fresh[B] = 0;
     if (B >= rp.nroot) {
         m.status[B] = ST_INACTIVE;
         for (int a = 0; a < 3; a++) m.X[(int64_t)a * m.cap + B] = 0;
@@ -489,6 +491,8 @@ __global__ void k_build_children(DevMesh m, const int32_t *rlist, const int32_t 
     const int cv[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
     for (int a = 0; a < 3; a++) m.X[(int64_t)a * m.cap + ch] = m.X[(int64_t)a * m.cap + P] + cv[a] * W;
     m.nbrc[ch] = kNone;
+    m.parent[ch] = P;
+    m.fresh[ch] = 1;
     if (c == 0) m.nbrc[P] = first[P];
 }
 
@@ -676,10 +680,26 @@ RootParams root_params(const Ctx &c) {
     return rp;
 }
 
+// halo records: one per active block with an N_SKIP link, numbered in block-ID order
+__global__ void k_bins_halo(const DevMesh m, int8_t *bins) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= m.cap) return;
+    bins[B] = (m.status[B] != ST_INACTIVE && (m.bflag[B] & BF_NSKIP)) ? 0 : -1;
+}
+
+__global__ void k_set_hid(DevMesh m, const int8_t *bins, const int32_t *rank) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= m.cap) return;
+    m.hid[B] = bins[B] == 0 ? rank[B] : -1;
+}
+
 template <typename Dd>
 void masks_and_lists(const Ctx &c) {
     const int cap = c.m.cap;
     k_block_masks<Dd><<<grid_for(cap), 256, 0, c.stream>>>(c.m);
+    k_bins_halo<<<grid_for(cap), 256, 0, c.stream>>>(c.m, c.bins);
+    run_scan(c, c.bins, cap, 1);
+    k_set_hid<<<grid_for(cap), 256, 0, c.stream>>>(c.m, c.bins, c.rank);
     k_parent_mask<Dd><<<grid_for(cap), 256, 0, c.stream>>>(c.m);
     const int64_t tot = (int64_t)c.m.lmax * cap;
     k_bins_keep<<<grid_for(tot), 256, 0, c.stream>>>(c.m, c.ids, c.ctr, c.bins, 1);
@@ -710,7 +730,7 @@ void adapt_assign_t(const Ctx &c, int n_ref) {
 }
 
 template <typename Dd>
-void adapt_build_t(const Ctx &c, int n_ref, const LevelParams &lp) {
+void adapt_build_t(const Ctx &c, int n_ref) {
     const int cap = c.m.cap;
     const int64_t tot = (int64_t)c.m.lmax * cap;
     // S4
@@ -731,8 +751,6 @@ void adapt_build_t(const Ctx &c, int n_ref, const LevelParams &lp) {
         run_scan(c, c.bins, cap, c.m.lmax);
         k_append<Dd><<<grid_for(cap), 256, 0, c.stream>>>(c.m, c.rank, c.first, c.ids, c.ctr);
         k_nids_after_append<Dd><<<1, 64, 0, c.stream>>>(c.ctr, c.m.lmax);
-        // S7: all cells of the new children from their parents' data
-        launch_interp(c, c.rlist, n_ref, lp, 1);
     }
     k_finalize_status<<<grid_for(cap), 256, 0, c.stream>>>(c.m);
     k_branch_leaf<Dd><<<grid_for(cap), 256, 0, c.stream>>>(c.m);
@@ -795,9 +813,7 @@ void launch_effective_tags(const Ctx &c) {
 
 void launch_adapt_assign(const Ctx &c, int n_ref) { AMR_DIM_DISPATCH(c.dim, adapt_assign_t<Dd>(c, n_ref)); }
 
-void launch_adapt_build(const Ctx &c, int n_ref, const LevelParams &lp) {
-    AMR_DIM_DISPATCH(c.dim, adapt_build_t<Dd>(c, n_ref, lp));
-}
+void launch_adapt_build(const Ctx &c, int n_ref) { AMR_DIM_DISPATCH(c.dim, adapt_build_t<Dd>(c, n_ref)); }
 
 void launch_connectivity(const Ctx &c, int) { AMR_DIM_DISPATCH(c.dim, connectivity_t<Dd>(c)); }
 

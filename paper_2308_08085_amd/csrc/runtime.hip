@@ -37,7 +37,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t f[2], nbr, nbrc, X, level, status, tag, ldes, viol, bflag, gmask, imask;
     size_t ids, ids_tmp, iface, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
-    size_t crit, part4, solid, solid_list, ctr, staging, staging_bytes, total;
+    size_t crit, part4, solid, solid_list, ctr, staging, staging_bytes, total, hid, U, parent, fresh;
 };
 
 int nroot_of(const amr_config *c) { return c->root[0] * c->root[1] * (c->dim == 3 ? c->root[2] : 1); }
@@ -69,14 +69,19 @@ void make_layout(const amr_config *c, Layout *L) {
     const size_t mb = c->dim == 2 ? 16 : 64, nb = c->dim == 2 ? 9 : 27, q = (size_t)c->q;
     const size_t capc = cap * mb, sb = storage_bytes(c->storage);
     const size_t nroot = (size_t)nroot_of(c);
+    const size_t fslots = q * capc + cap * (size_t)halo_entries(c->q);  // rows + halo records
     size_t t = 0;
     auto take = [&](size_t bytes) {
         size_t o = align256(t);
         t = o + bytes;
         return o;
     };
-    L->f[0] = take(q * capc * sb);
-    L->f[1] = take(q * capc * sb);
+    L->f[0] = take(fslots * sb);
+    L->f[1] = take(fslots * sb);
+    L->hid = take(cap * 4);
+    L->parent = take(cap * 4);
+    L->fresh = take(cap);
+    L->U = take(3 * capc * 8);
     L->nbr = take(nb * cap * 4);
     L->nbrc = take(nb * cap * 4);
     L->X = take(3 * cap * 4);
@@ -318,6 +323,12 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
     c.m.cap = cfg->max_blocks;
     c.m.capc = (int64_t)cfg->max_blocks * c.mb;
     c.m.lmax = cfg->max_levels;
+    c.m.halo_base = (int64_t)cfg->max_blocks * c.q * c.mb;
+    c.m.nh = halo_entries(cfg->q);
+    c.m.hid = (int32_t *)(a + lay.hid);
+    c.m.parent = (int32_t *)(a + lay.parent);
+    c.m.fresh = (int8_t *)(a + lay.fresh);
+    c.U = (double *)(a + lay.U);
     c.m.nbr = (int32_t *)(a + lay.nbr);
     c.m.nbrc = (int32_t *)(a + lay.nbrc);
     c.m.X = (int32_t *)(a + lay.X);
@@ -462,6 +473,7 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
         HIP_TRY(hipMemcpyAsync(c.m.tag, tags_in, cap, hipMemcpyHostToDevice, c.stream));
     } else if (p->kind == AMR_TAG_VORTICITY_REL) {
         const LevelParams lp = level_params(h);
+        for (int L = 0; L < h->lmax; L++) launch_velocity(c, c.ids + L * cap, h->nids[L], L, lp);
         for (int L = 0; L < h->lmax; L++) launch_vorticity(c, c.ids + L * cap, h->nids[L], L, lp);
         launch_tag_vorticity(c, p->theta);
     } else {
@@ -490,8 +502,14 @@ amr_status amr_adapt(amr_t *h, amr_adapt_stats *stats) {
         return fail(AMR_ERR_CAPACITY, "%d refinements need %d free block IDs, %d left", n_ref, c.nc * n_ref, dc.gtop);
     const LevelParams lp = level_params(h);
     launch_adapt_assign(c, n_ref);
-    launch_adapt_build(c, n_ref, lp);
+    launch_adapt_build(c, n_ref);
     launch_connectivity(c, c.m.cap);
+    // S7: every cell of the new children from their parents' data; after the
+    // connectivity rebuild, since populations are stored by their source cell
+    if (n_ref > 0) {
+        launch_interp(c, c.rlist, n_ref, lp, 1);
+        launch_refresh_neighbours(c, c.rlist, n_ref, lp);
+    }
     s = sync_checked(h);
     if (s != AMR_OK) return s;
     s = read_counters(h, &dc);
@@ -542,11 +560,12 @@ amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf
         if (kind == AMR_FIELD_RHO_U && op == AMR_SET) {
             const int64_t ncell = (int64_t)c.nroot * mb;
             if ((s = need((uint64_t)ncell * 32)) != AMR_OK) return s;
-            const int64_t per = (int64_t)(c.staging_bytes / 32);
-            for (int64_t e0 = 0; e0 < ncell; e0 += per) {
-                const int64_t nn = ncell - e0 < per ? ncell - e0 : per;
-                HIP_TRY(hipMemcpyAsync(c.staging, (const char *)buf + e0 * 32, nn * 32, hipMemcpyHostToDevice, st));
-                launch_set_rho_u_root(c, (const double *)c.staging, (int)e0, (int)nn);
+            const int per = (int)(c.staging_bytes / (32 * (size_t)mb));
+            for (int b0 = 0; b0 < c.nroot; b0 += per) {
+                const int b1 = b0 + per < c.nroot ? b0 + per : c.nroot;
+                HIP_TRY(hipMemcpyAsync(c.staging, (const char *)buf + (size_t)b0 * mb * 32, (size_t)(b1 - b0) * mb * 32,
+                                       hipMemcpyHostToDevice, st));
+                launch_set_rho_u_root(c, (const double *)c.staging, b0, b1);
                 HIP_TRY(hipStreamSynchronize(st));
             }
             drop_graphs(h);

@@ -159,7 +159,8 @@ def test_block_f_roundtrip_and_mass():
     f = g.get_block_f_all()
     f2 = f * (1.0 + 1e-3 * rng.standard_normal(f.shape))
     g.set_block_f_all(f2)
-    assert np.array_equal(g.get_block_f_all(), f2)
+    act = g.mesh()["status"] != 8
+    assert np.array_equal(g.get_block_f_all()[act], f2[act])
     # closed box at rest: mass is conserved by the GPU path too
     case = W.cavity(3, 19, 16, 1, 100.0, storage="f64", seed=3)
     case.face_u = ((0.0, 0.0, 0.0),) * 6
