@@ -1,14 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X AMR lattice Boltzmann path (one JSON line on stdout).
 
-Workload: the D3Q19 BGK lid-driven cube cavity, 64^3 root cells (16^3 blocks of
-4^3 cells), 3 grid levels, Re 400, lid speed 0.05, vorticity-threshold
-refinement (theta = 0.1) every 50 coarse steps, seeded +-1e-4 velocity noise.
-One benchmark "step" is one pass of the whole hot path: 50 coarse time steps
-(recursive sub-cycled collide/stream, interpolation, averaging) followed by one
-adaptation cycle (pre-adaptation sync, criterion, tagging, refine/coarsen,
-connectivity rebuild).  It runs with FP32 shifted storage (the reported value)
-and with FP16 shifted storage.
+Main workload: D3Q27 BGK flow past a square-section cylinder, 256x128x128 root
+cells (64x32x32 blocks of 4^3 cells), cylinder side 16 spanning z at x = 64,
+inlet u = 0.05, Re 200, 3 levels; static near-wall refinement at t = 0 (frozen)
+and vorticity-threshold refinement (theta = 0.1) every 32 coarse steps.  It runs
+with FP32 shifted storage (the reported value) and with FP16 shifted storage.
+Also reported: the D3Q19 lid-driven cube cavity (64^3 root cells, 3 levels,
+Re 400, adaptation every 50 coarse steps).
+
+One benchmark "step" is one pass of the whole hot path: one adaptation period of
+coarse time steps (recursive sub-cycled collide/stream, interpolation,
+averaging) followed by one adaptation cycle (pre-adaptation sync, criterion,
+tagging, refine/coarsen, connectivity rebuild).
 
 value = million lattice-node updates per second of the advancement, counted with
 the paper's AMR weighting (Sec. "Solver Performance"), adaptation excluded as
@@ -36,21 +40,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_storage(case, storage, steps, warmup, theta, profile_periods=2):
+def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=True):
     import torch
     from paper_2308_08085_amd import abi, workloads as W
 
     g = abi.AmrLbm(case, storage=storage)
     g.set_root_rho_u(case.initial_rho_u())
+    for _ in range(case.dist_levels):  # static near-wall refinement at t = 0
+        g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=1)
+        g.adapt()
     period = case.adapt_every
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
 
-    def one_period(profile=False):
+    def one_period(profile=False, check=False):
         counts = g.counts().copy()
         ev0.record(g.stream)
-        g.step(period, profile=profile)
+        g.step(period, profile=profile, graph=graph and not profile, check_finite=check)
         ev1.record(g.stream)
+        g.synchronize()  # the adaptation clock starts once the advancement has finished
         t0 = time.perf_counter()
         g.tag(abi.TAG_VORTICITY_REL, theta=theta)
         g.adapt()
@@ -59,7 +67,7 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2):
         return period * W.mlups_updates(counts, case.dim), adv_ms, t_adapt * 1e3, counts
 
     for i in range(warmup):
-        u, ms, ams, counts = one_period()
+        u, ms, ams, counts = one_period(check=(i == warmup - 1))
         log("[%s] warmup %d/%d: %.1f MLUPS, adapt %.2f ms, blocks/level %s" %
             (storage, i + 1, warmup, u / ms / 1e3, ams, counts.tolist()))
     torch.cuda.synchronize()
@@ -94,12 +102,12 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2):
     return out
 
 
-def roofline(res):
+def roofline(res, kernel):
     k = res["kernels"]["collide_stream"]
     gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_collide_stream<19, F32S>",
+            "kernel": kernel,
             "avg_launch_us": round(k["ms"] * 1e3 / max(k["launches"], 1), 2),
             "bytes_per_launch": round(k["bytes"] / max(k["launches"], 1))}
 
@@ -143,7 +151,7 @@ def cpu_baseline(theta, seconds=20.0):
     import oracle
     from paper_2308_08085_amd import workloads as W
 
-    case = W.config2()
+    case = W.config4()
     o = oracle.Oracle(case)
     o.set_root_rho_u(case.initial_rho_u())
     tot_u = tot_s = 0.0
@@ -162,15 +170,15 @@ def cpu_baseline(theta, seconds=20.0):
         tot_u += W.mlups_updates(c, case.dim)
         tot_s += dt
         n += 1
-        if n == 10 and adapt_s is None:
+        if n == 2 and adapt_s is None:
             t0 = time.perf_counter()
             o.tag(kind=0, theta=theta)
             o.adapt()
             adapt_s = time.perf_counter() - t0
     return {"value": round(tot_u / tot_s / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "adapt_ms_per_cycle": round(adapt_s * 1e3, 1) if adapt_s else None,
-            "sample": "same cavity set-up, FP64 oracle, one thread: %d coarse steps from the initial field "
-                      "with one vorticity adaptation after step 10 (%.1f s of stepping)" % (n, tot_s)}
+            "sample": "same cylinder set-up, FP64 oracle, one thread: %d coarse steps from the initial field "
+                      "with one vorticity adaptation after step 2 (%.1f s of stepping)" % (n, tot_s)}
 
 
 def main():
@@ -181,6 +189,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-leg", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-cavity", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -189,11 +198,14 @@ def main():
     from paper_2308_08085_amd import abi, workloads as W
 
     abi.load()
-    case = W.config2()
-    theta = case.theta
     log("device:", torch.cuda.get_device_name(0))
-    r32 = run_storage(case, "f32s", args.steps, args.warmup, theta)
-    r16 = None if args.no_fp16 else run_storage(case, "f16s", args.steps, args.warmup, theta)
+    main_case = W.config4(cap=W.config4().nroot * 16)
+    cav = W.config2()
+    theta = main_case.theta
+    r32 = run_storage(main_case, "f32s", args.steps, args.warmup, theta)
+    r16 = None if args.no_fp16 else run_storage(main_case, "f16s", args.steps, args.warmup, theta)
+    c32 = None if args.no_cavity else run_storage(cav, "f32s", args.steps, args.warmup, theta)
+    c16 = None if (args.no_cavity or args.no_fp16) else run_storage(cav, "f16s", args.steps, args.warmup, theta)
     err = None if args.no_error_leg else error_leg(theta)
     cpu = None if args.no_cpu_baseline else cpu_baseline(theta)
     line = {
@@ -210,20 +222,30 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "D3Q19 BGK lid-driven cube cavity, 64^3 root cells (16^3 blocks of 4^3), 3 levels, "
-                        "Re 400, lid u 0.05, vorticity tagging theta 0.1 every 50 coarse steps; FP32 shifted storage",
-            "step": "50 coarse steps + 1 adaptation cycle",
+            "workload": "D3Q27 BGK flow past a square cylinder, 256x128x128 root cells (64x32x32 blocks of 4^3), "
+                        "cylinder side 16 at x = 64 spanning z, inlet u 0.05, Re 200, 3 levels, near-wall "
+                        "refinement at t = 0 + vorticity tagging theta 0.1 every 32 coarse steps; FP32 shifted storage",
+            "step": "32 coarse steps + 1 adaptation cycle",
             "level_blocks_end": r32["level_blocks"],
         },
         "adapt_ms_per_cycle": round(r32["adapt_ms_per_cycle"], 3),
         "mlups_incl_adapt": round(r32["mlups_wall"], 1),
-        "roofline": roofline(r32),
+        "roofline": roofline(r32, "k_collide_stream<27, F32S>"),
         "cpu_baseline": cpu,
     }
     if r16 is not None:
         line["fp16s"] = {"mlups": round(r16["mlups"], 1), "adapt_ms_per_cycle": round(r16["adapt_ms_per_cycle"], 3),
                          "speedup_vs_fp32": round(r16["mlups"] / r32["mlups"], 3),
-                         "roofline_frac": roofline(r16)["frac"], "level_blocks_end": r16["level_blocks"]}
+                         "roofline": roofline(r16, "k_collide_stream<27, F16S>"),
+                         "level_blocks_end": r16["level_blocks"]}
+    if c32 is not None:
+        line["cavity_d3q19"] = {
+            "workload": "D3Q19 lid-driven cube cavity, 64^3 root cells, 3 levels, Re 400, adapt every 50",
+            "mlups_f32s": round(c32["mlups"], 1), "adapt_ms_per_cycle_f32s": round(c32["adapt_ms_per_cycle"], 3),
+            "roofline_f32s": roofline(c32, "k_collide_stream<19, F32S>"), "level_blocks_end": c32["level_blocks"]}
+        if c16 is not None:
+            line["cavity_d3q19"]["mlups_f16s"] = round(c16["mlups"], 1)
+            line["cavity_d3q19"]["speedup_f16s_vs_f32s"] = round(c16["mlups"] / c32["mlups"], 3)
     if err is not None:
         line["error_vs_fp64_oracle"] = err
     print(json.dumps(line), flush=True)

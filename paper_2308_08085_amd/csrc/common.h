@@ -73,7 +73,7 @@ template <> struct Lat<27> : D3 {
 // index of the neighbour region with per-axis offsets r in {-1,0,1}, as a
 // position 0..26 in (x fastest) offset order; LDS link tables are kept in this
 // order so kernels can look links up arithmetically
-__host__ __device__ inline int offset_slot(int rx, int ry, int rz) { return (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1); }
+__host__ __device__ constexpr int offset_slot(int rx, int ry, int rz) { return (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1); }
 
 // region slot (in the lattice's own link-table numbering: 0..8 in 2-D,
 // 0..26 in 3-D) of a cell position given in local block coordinates that may

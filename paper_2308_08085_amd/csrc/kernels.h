@@ -33,6 +33,7 @@ struct Ctx {
     int32_t *ids;        // [lmax][cap]
     int32_t *ids_tmp;    // [lmax][cap]
     int32_t *iface;      // [lmax][cap]
+    int32_t *order;      // [lmax][cap] solver launch order per level (Morton)
     int32_t *gap;        // [cap]
     int32_t *first;      // [cap]
     int32_t *rank;       // [lmax * cap]

@@ -85,6 +85,53 @@ __device__ __forceinline__ void scatter_cell(const DevMesh &m, const int32_t *li
     for (int p = 0; p < Lt::Q; p++) store_g<Lt, ST>(f, entry_slot<Lt>(m, link, B, h, p, l), p, g[p]);
 }
 
+// Source block of population p (velocity c) for a cell of an interior 3-D
+// block, from the wave-uniform region links nb[27]: wx/wy/wz say whether the
+// source cell x - c lies across the block face along that axis.
+template <int CX, int CY, int CZ>
+__device__ __forceinline__ int32_t pick_src(const int32_t *nb, bool wx, bool wy, bool wz) {
+    // plain values first: a conditional over two array elements would be an
+    // lvalue and turn into a runtime index into the array
+    const int32_t n000 = nb[offset_slot(0, 0, 0)], n100 = nb[offset_slot(-CX, 0, 0)];
+    const int32_t n010 = nb[offset_slot(0, -CY, 0)], n110 = nb[offset_slot(-CX, -CY, 0)];
+    const int32_t n001 = nb[offset_slot(0, 0, -CZ)], n101 = nb[offset_slot(-CX, 0, -CZ)];
+    const int32_t n011 = nb[offset_slot(0, -CY, -CZ)], n111 = nb[offset_slot(-CX, -CY, -CZ)];
+    const int32_t a = wx ? n100 : n000, b = wx ? n110 : n010;
+    const int32_t c = wx ? n101 : n001, d = wx ? n111 : n011;
+    const int32_t z0 = wy ? b : a, z1 = wy ? d : c;
+    return wz ? z1 : z0;
+}
+
+template <typename Lt, int P>
+__device__ __forceinline__ int64_t interior_slot(const int32_t *nb, int i, int j, int k) {
+    constexpr int cx = Lt::cx(P), cy = Lt::cy(P), cz = Lt::cz(P);
+    const bool wx = (cx > 0 && i == 0) || (cx < 0 && i == 3);
+    const bool wy = (cy > 0 && j == 0) || (cy < 0 && j == 3);
+    const bool wz = (cz > 0 && k == 0) || (cz < 0 && k == 3);
+    const int32_t id = pick_src<cx, cy, cz>(nb, wx, wy, wz);
+    const int ls = ((i - cx) & 3) + 4 * ((j - cy) & 3) + 16 * ((k - cz) & 3);
+    return (int64_t)id * (Lt::Q * Lt::MB) + (P * Lt::MB + ls);
+}
+
+// wave-uniform copies of the 27 region links (constant indices throughout, so
+// the array lives in scalar registers)
+template <int R>
+__device__ __forceinline__ void uniform_links(const int32_t *link, int32_t *nb) {
+    if constexpr (R < 27) {
+        nb[R] = __builtin_amdgcn_readfirstlane(link[R]);
+        uniform_links<R + 1>(link, nb);
+    }
+}
+
+template <typename Lt, typename ST, int P>
+__device__ __forceinline__ void gather_interior(const int32_t *nb, int i, int j, int k,
+                                                const typename ST::T *f, typename ST::R *g) {
+    if constexpr (P < Lt::Q) {
+        g[P] = load_g<Lt, ST>(f, interior_slot<Lt, P>(nb, i, j, k), P);
+        gather_interior<Lt, ST, P + 1>(nb, i, j, k, f, g);
+    }
+}
+
 // Per-workgroup staging of NBLK block descriptors; links by region slot.
 template <typename Lt, int NBLK>
 struct BlockStage {
@@ -142,11 +189,29 @@ __global__ __launch_bounds__(256) void k_collide_stream(const int32_t *__restric
     const int i = l & 3, j = (l >> 2) & 3, k = l >> 4;
 
     R g[Q];
-    gather_cell<Lt, ST>(m, link, B, h, l, src, g);
     R drho, ux, uy, uz;
+    const R om = R(omega_d);
+    if constexpr (Lt::D == 3) {
+        // Interior block (every region link a same-level block): one block per
+        // wave, so the links are wave-uniform and every source is a select.
+        if (!(flag & (BF_BOUNDARY | BF_NSKIP))) {
+            int32_t nb[27];
+            uniform_links<0>(link, nb);
+            gather_interior<Lt, ST, 0>(nb, i, j, k, src, g);
+            moments_g<Lt, R>(g, drho, ux, uy, uz);
+            const R uu = ux * ux + uy * uy + uz * uz;
+            const int Bu = nb[13];
+#pragma unroll
+            for (int p = 0; p < Q; p++) {
+                g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
+                store_g<Lt, ST>(dst, mslot<Lt>(Bu, p, l), p, g[p]);
+            }
+            return;
+        }
+    }
+    gather_cell<Lt, ST>(m, link, B, h, l, src, g);
     moments_g<Lt, R>(g, drho, ux, uy, uz);
     const R uu = ux * ux + uy * uy + uz * uz;
-    const R om = R(omega_d);
 #pragma unroll
     for (int p = 0; p < Q; p++) g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
 

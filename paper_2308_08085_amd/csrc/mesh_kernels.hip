@@ -693,6 +693,42 @@ __global__ void k_set_hid(DevMesh m, const int8_t *bins, const int32_t *rank) {
     m.hid[B] = bins[B] == 0 ? rank[B] : -1;
 }
 
+// Launch order of level L+1 from that of level L: the children of every
+// refined block, in its order (children are numbered as Morton digits).
+__global__ void k_bins_order(const DevMesh m, const int32_t *order, const DevCounters *ctr, int L, int8_t *bins) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= m.cap) return;
+    int8_t b = -1;
+    if (n < ctr->nids[L]) {
+        const int32_t first = m.nbrc[order[n]];
+        if (first >= 0 && first < m.cap) b = 0;
+    }
+    bins[n] = b;
+}
+
+template <typename Dd>
+__global__ void k_expand_order(const DevMesh m, const int32_t *order, const int8_t *bins, const int32_t *rank,
+                               int32_t *next) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)m.cap * Dd::NC) return;
+    const int n = (int)(e / Dd::NC), c = (int)(e - (int64_t)n * Dd::NC);
+    if (bins[n] != 0) return;
+    const int64_t at = (int64_t)rank[n] * Dd::NC + c;
+    if (at < m.cap) next[at] = m.nbrc[order[n]] + c;
+}
+
+template <typename Dd>
+void build_order(const Ctx &c) {
+    const int cap = c.m.cap;
+    for (int L = 0; L + 1 < c.m.lmax; L++) {
+        const int32_t *cur = c.order + (size_t)L * cap;
+        k_bins_order<<<grid_for(cap), 256, 0, c.stream>>>(c.m, cur, c.ctr, L, c.bins);
+        run_scan(c, c.bins, cap, 1);
+        k_expand_order<Dd><<<grid_for((int64_t)cap * Dd::NC), 256, 0, c.stream>>>(c.m, cur, c.bins, c.rank,
+                                                                                  c.order + (size_t)(L + 1) * cap);
+    }
+}
+
 template <typename Dd>
 void masks_and_lists(const Ctx &c) {
     const int cap = c.m.cap;
@@ -706,6 +742,7 @@ void masks_and_lists(const Ctx &c) {
     run_scan(c, c.bins, tot, c.m.lmax);
     k_compact<<<grid_for(tot), 256, 0, c.stream>>>(c.bins, c.rank, c.ids, c.ids_tmp, cap, tot);
     k_copy_lists<<<grid_for(tot), 256, 0, c.stream>>>(c.ids_tmp, c.iface, cap, c.m.lmax, c.ctr, 0);
+    build_order<Dd>(c);
 }
 
 template <typename Dd>

@@ -1,11 +1,13 @@
 // runtime.hip -- host runtime behind the C ABI of include/amr_lbm.h: arena
 // carve-up, the recursive sub-cycled schedule (optionally replayed from a HIP
 // graph), tagging and adaptation sequencing, field access.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "kernels.h"
@@ -36,7 +38,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     size_t f[2], nbr, nbrc, X, level, status, tag, ldes, viol, bflag, gmask, imask;
-    size_t ids, ids_tmp, iface, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
+    size_t ids, ids_tmp, iface, order, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
     size_t crit, part4, solid, solid_list, ctr, staging, staging_bytes, total, hid, U, parent, fresh;
 };
 
@@ -96,6 +98,7 @@ void make_layout(const amr_config *c, Layout *L) {
     L->ids = take(lmax * cap * 4);
     L->ids_tmp = take(lmax * cap * 4);
     L->iface = take(lmax * cap * 4);
+    L->order = take(lmax * cap * 4);
     L->gap = take(cap * 4);
     L->first = take(cap * 4);
     L->rlist = take(cap * 4);
@@ -193,7 +196,7 @@ void timed_launch(amr_handle *h, int kind, int blocks, F &&fn) {
 void collide_stream(amr_handle *h, int L) {
     const LevelParams lp = level_params(h);
     timed_launch(h, 0, h->nids[L], [&] {
-        launch_collide_stream(h->c, h->c.ids + (size_t)L * h->c.m.cap, h->nids[L], L, lp, h->bc);
+        launch_collide_stream(h->c, h->c.order + (size_t)L * h->c.m.cap, h->nids[L], L, lp, h->bc);
     });
     h->par[L] ^= 1;
 }
@@ -345,6 +348,7 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
     c.ids = (int32_t *)(a + lay.ids);
     c.ids_tmp = (int32_t *)(a + lay.ids_tmp);
     c.iface = (int32_t *)(a + lay.iface);
+    c.order = (int32_t *)(a + lay.order);
     c.gap = (int32_t *)(a + lay.gap);
     c.first = (int32_t *)(a + lay.first);
     c.rlist = (int32_t *)(a + lay.rlist);
@@ -371,8 +375,30 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
         h->tau[L] = 0.5 + std::ldexp(tau0 - 0.5, L);  // tau*_L = 1/2 + 2^L (tau*_0 - 1/2)
         h->par[L] = 0;
     }
-    hipError_t e = hipSuccess;
-    if (!h->solid.empty()) {
+    // level-0 launch order: the active root blocks along the Morton curve of
+    // their root coordinates; the finer levels inherit it (child index =
+    // Morton digit), so blocks processed together are spatial neighbours
+    std::vector<int32_t> root_order;
+    {
+        std::vector<std::pair<uint64_t, int32_t>> keyed;
+        for (int B = 0; B < nroot; B++) {
+            if (!h->solid.empty() && h->solid[B]) continue;
+            const uint32_t x[3] = {(uint32_t)(B % c.root[0]), (uint32_t)((B / c.root[0]) % c.root[1]),
+                                   (uint32_t)(B / (c.root[0] * c.root[1]))};
+            uint64_t key = 0;
+            for (int bit = 0; bit < 21; bit++)
+                for (int ax = 0; ax < c.dim; ax++) key |= (uint64_t)((x[ax] >> bit) & 1u) << (bit * c.dim + ax);
+            keyed.push_back({key, B});
+        }
+        std::stable_sort(keyed.begin(), keyed.end(),
+                         [](const std::pair<uint64_t, int32_t> &a, const std::pair<uint64_t, int32_t> &b) {
+                             return a.first < b.first;
+                         });
+        for (auto &kv : keyed) root_order.push_back(kv.second);
+    }
+    hipError_t e = hipMemcpyAsync(c.order, root_order.data(), root_order.size() * 4, hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    if (e == hipSuccess && !h->solid.empty()) {
         e = hipMemcpyAsync(c.solid, h->solid.data(), h->solid.size(), hipMemcpyHostToDevice, c.stream);
         if (e == hipSuccess && !slist.empty())
             e = hipMemcpyAsync(c.solid_list, slist.data(), slist.size() * 4, hipMemcpyHostToDevice, c.stream);
