@@ -210,6 +210,61 @@ amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf
  * synchronised first.  NULL is accepted. */
 amr_status amr_destroy(amr_t *h);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent simulations advanced together.  Not part of the
+ * paper's method, which advances one forest; each member keeps its own block-ID
+ * space, tables and adaptation (amr_tag / amr_adapt / amr_fields on its own
+ * handle), and a batch step gives every member exactly the result of the same
+ * number of lbm_step calls on it alone.  Members of equal lattice and storage
+ * advance each level sweep in one persistent launch (collide-stream, ghost
+ * interpolation, interface averaging); the work lists are rebuilt on the
+ * device from the members' own lists at the start of every coarse step, so a
+ * captured coarse step stays valid while members adapt between batch steps. */
+typedef struct amr_batch amr_batch_t;
+
+typedef struct {
+    int32_t threads;    /* threads per workgroup of the collide-stream launches: 64, 128 or 256
+                           (3-D: 1, 2 or 4 blocks per workgroup; 2-D: 4, 8 or 16) */
+    int32_t wg_per_cu;  /* persistent grid = wg_per_cu x compute units, 1 .. 64 */
+    int32_t schedule;   /* 0: groups of different lattice/storage one after another;
+                           1: each group on its own concurrent branch of the step */
+} amr_batch_tuning;
+
+/* Device arena a batch of `n` simulations needs (descriptors and work lists).
+ * Errors: AMR_ERR_ARG. */
+amr_status amr_batch_query_bytes(amr_t *const *sims, int32_t n, uint64_t *arena_bytes);
+
+/* Group `n` existing simulations (host array of handles, copied) into a batch
+ * on the caller's arena (256-byte aligned, at least amr_batch_query_bytes) and
+ * stream.  Every member must have been created on `hip_stream` and have made
+ * the same number of coarse steps modulo 2; at most 255 members per lattice
+ * and storage, each with max_blocks <= 2^24.  The members must outlive the
+ * batch.  Default tuning: 256 threads, 8 workgroups per CU, schedule 0.
+ * Errors: AMR_ERR_ARG, AMR_ERR_STATE, AMR_ERR_CAPACITY, AMR_ERR_DEVICE. */
+amr_status amr_batch_create(amr_t *const *sims, int32_t n, void *dev_arena, uint64_t arena_bytes, void *hip_stream,
+                            amr_batch_t **out);
+
+/* Advance every member n coarse steps (flags: AMR_USE_GRAPH, AMR_CHECK_FINITE;
+ * AMR_PROFILE is refused).  After a batch step the members must not be stepped
+ * alone before the next batch step unless by an even number of coarse steps.
+ * Errors: AMR_ERR_ARG, AMR_ERR_STATE, AMR_ERR_UNSTABLE (first non-finite
+ * member named in amr_last_error), AMR_ERR_DEVICE. */
+amr_status amr_batch_step(amr_batch_t *b, int32_t n_coarse_steps, uint32_t flags);
+
+/* Launch shape of the batch (drops its captured graphs).  Errors: AMR_ERR_ARG. */
+amr_status amr_batch_set_tuning(amr_batch_t *b, const amr_batch_tuning *t);
+amr_status amr_batch_get_tuning(amr_batch_t *b, amr_batch_tuning *t);
+
+/* Time every launch shape (threads x wg_per_cu x schedule) over `trial_steps`
+ * graph-replayed coarse steps each, keep the fastest and return it with its
+ * time per coarse step.  The members advance (2 + trial_steps) coarse steps
+ * per shape tried; results do not depend on the shape.
+ * Errors: AMR_ERR_ARG, AMR_ERR_STATE, AMR_ERR_DEVICE. */
+amr_status amr_batch_autotune(amr_batch_t *b, int32_t trial_steps, amr_batch_tuning *best, double *best_ms);
+
+/* Release the batch (members and arena stay the caller's).  NULL is accepted. */
+amr_status amr_batch_destroy(amr_batch_t *b);
+
 /* Message of the last error raised on the calling thread ("" if none). */
 const char *amr_last_error(void);
 

@@ -25,7 +25,8 @@ TAG_VORTICITY_REL, TAG_DISTANCE = 0, 1
 
 # every symbol the header declares
 EXPORTS = ("amr_query_bytes", "amr_create", "amr_tag", "amr_adapt", "lbm_step", "amr_fields", "amr_destroy",
-           "amr_last_error")
+           "amr_batch_query_bytes", "amr_batch_create", "amr_batch_step", "amr_batch_set_tuning",
+           "amr_batch_get_tuning", "amr_batch_autotune", "amr_batch_destroy", "amr_last_error")
 
 
 class AmrError(RuntimeError):
@@ -52,6 +53,10 @@ class AdaptStats(C.Structure):
                 ("n_free", C.c_int32), ("level_blocks", C.c_int32 * 8)]
 
 
+class BatchTuning(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("wg_per_cu", C.c_int32), ("schedule", C.c_int32)]
+
+
 _lib = None
 
 
@@ -70,6 +75,13 @@ def load():
         L.lbm_step.argtypes = [P, C.c_int32, C.c_uint32]
         L.amr_fields.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, C.c_uint64]
         L.amr_destroy.argtypes = [P]
+        L.amr_batch_query_bytes.argtypes = [C.POINTER(P), C.c_int32, C.POINTER(C.c_uint64)]
+        L.amr_batch_create.argtypes = [C.POINTER(P), C.c_int32, P, C.c_uint64, P, C.POINTER(P)]
+        L.amr_batch_step.argtypes = [P, C.c_int32, C.c_uint32]
+        L.amr_batch_set_tuning.argtypes = [P, C.POINTER(BatchTuning)]
+        L.amr_batch_get_tuning.argtypes = [P, C.POINTER(BatchTuning)]
+        L.amr_batch_autotune.argtypes = [P, C.c_int32, C.POINTER(BatchTuning), C.POINTER(C.c_double)]
+        L.amr_batch_destroy.argtypes = [P]
         L.amr_last_error.restype = C.c_char_p
         for n in EXPORTS[:-1]:
             getattr(L, n).restype = C.c_int32
@@ -111,7 +123,7 @@ def query_bytes(case, storage=None) -> int:
 class AmrLbm:
     """One simulation on the GPU behind the C ABI."""
 
-    def __init__(self, case, storage=None, device="cuda"):
+    def __init__(self, case, storage=None, device="cuda", stream=None):
         import torch
         self.case = case
         self.storage = storage or case.storage
@@ -130,7 +142,7 @@ class AmrLbm:
         self.arena = torch.empty(self.arena_bytes + 256, dtype=torch.uint8, device=device)
         base = self.arena.data_ptr()
         aligned = (base + 255) & ~255
-        self.stream = torch.cuda.Stream(device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         h = C.c_void_p(0)
         _check(lib.amr_create(C.byref(cfg), C.c_void_p(aligned), C.c_uint64(self.arena_bytes),
                               C.c_void_p(self.stream.cuda_stream), C.byref(h)))
@@ -233,3 +245,58 @@ class AmrLbm:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+class AmrBatch:
+    """Several AmrLbm simulations (created on one shared stream) advanced together."""
+
+    def __init__(self, sims, device="cuda"):
+        import torch
+        self.sims = list(sims)
+        lib = load()
+        handles = (C.c_void_p * len(self.sims))(*[s._h.value for s in self.sims])
+        self._handles = handles
+        nbytes = C.c_uint64(0)
+        _check(lib.amr_batch_query_bytes(handles, len(self.sims), C.byref(nbytes)))
+        self.arena_bytes = int(nbytes.value)
+        self.arena = torch.empty(self.arena_bytes + 256, dtype=torch.uint8, device=device)
+        aligned = (self.arena.data_ptr() + 255) & ~255
+        self.stream = self.sims[0].stream
+        h = C.c_void_p(0)
+        _check(lib.amr_batch_create(handles, len(self.sims), C.c_void_p(aligned), C.c_uint64(self.arena_bytes),
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def step(self, n=1, graph=True, check_finite=False):
+        flags = (AMR_USE_GRAPH if graph else 0) | (AMR_CHECK_FINITE if check_finite else 0)
+        _check(load().amr_batch_step(self._h, int(n), flags))
+
+    def set_tuning(self, threads=256, wg_per_cu=8, schedule=0):
+        t = BatchTuning(int(threads), int(wg_per_cu), int(schedule))
+        _check(load().amr_batch_set_tuning(self._h, C.byref(t)))
+
+    def tuning(self):
+        t = BatchTuning()
+        _check(load().amr_batch_get_tuning(self._h, C.byref(t)))
+        return {"threads": t.threads, "wg_per_cu": t.wg_per_cu, "schedule": t.schedule}
+
+    def autotune(self, trial_steps=4):
+        t = BatchTuning()
+        ms = C.c_double(0)
+        _check(load().amr_batch_autotune(self._h, int(trial_steps), C.byref(t), C.byref(ms)))
+        return {"threads": t.threads, "wg_per_cu": t.wg_per_cu, "schedule": t.schedule}, float(ms.value)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            load().amr_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

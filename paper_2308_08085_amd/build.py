@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libamrlbm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["lbm_kernels.hip", "mesh_kernels.hip", "runtime.hip"]
+SOURCES = ["lbm_kernels.hip", "mesh_kernels.hip", "runtime.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

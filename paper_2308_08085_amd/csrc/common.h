@@ -183,6 +183,26 @@ struct LevelParams {
     double r_fc[kMaxLevels];     // fine->coarse rescaling of level L+1 -> L
 };
 
+// One simulation of a batch, as the fused solver kernels see it: its mesh
+// views, both distribution buffers, relaxation and rescaling parameters,
+// boundary conditions, and its launch-order / interface lists with their
+// on-device counts.
+struct SimDesc {
+    DevMesh m;
+    void *f[2];
+    LevelParams lp;
+    BCParams bc;
+    const int32_t *order;   // [lmax][cap]
+    const int32_t *iface;   // [lmax][cap]
+    const int32_t *nids;    // [kMaxLevels] on the device
+    const int32_t *niface;  // [kMaxLevels] on the device
+};
+
+// batch work item: simulation index in the top 8 bits, block ID below
+constexpr int kItemSimShift = 24;
+constexpr uint32_t kItemBlockMask = (1u << kItemSimShift) - 1u;
+constexpr int kMaxBatchSims = 255;
+
 // XCD-aware workgroup order: dispatch places workgroup w on XCD (w mod 8);
 // give each XCD a contiguous range of work so neighbouring blocks share an L2.
 __device__ inline int xcd_remap(int wg, int nwg) {

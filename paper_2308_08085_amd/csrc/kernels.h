@@ -74,6 +74,18 @@ void launch_block_f(const Ctx &c, int set, int b0, int b1, double *stage, const 
 void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, void *stage, const LevelParams &lp);
 void launch_mass(const Ctx &c, const LevelParams &lp);
 
+// ---- batched solver launches: one persistent launch per level over every
+// simulation of a batch (items = simulation << 24 | block, counts on the device)
+void launch_collide_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
+                          const int32_t *count, int L, int par, int nt, int grid);
+void launch_interp_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
+                         const int32_t *count, int L, int par0, int par1, int grid);
+void launch_average_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
+                          const int32_t *count, int L, int par0, int par1, int grid);
+// items[(2 L + kind) * stride + ...], counts[2 L + kind]: kind 0 launch order, 1 interface parents
+void launch_batch_items(hipStream_t stream, const SimDesc *sims, int nsims, int lmax, int cap_max, uint32_t *items,
+                        int64_t stride, int32_t *counts);
+
 // ---- mesh kernels (mesh_kernels.hip) ----
 void launch_init_mesh(const Ctx &c);
 void launch_crit_reset(const Ctx &c);

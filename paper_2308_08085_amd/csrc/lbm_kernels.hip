@@ -6,6 +6,8 @@
 //
 // Distributions are stored source-indexed in block-major rows (see common.h):
 // every kernel finds population p of a cell with entry_slot().
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace amr {
@@ -133,28 +135,100 @@ __device__ __forceinline__ void gather_interior(const int32_t *nb, int i, int j,
 }
 
 // Per-workgroup staging of NBLK block descriptors; links by region slot.
+// sim[] names the simulation of each entry in the batched kernels.
 template <typename Lt, int NBLK>
 struct BlockStage {
     static constexpr int NS = Lt::D == 2 ? 9 : 27;
     int32_t link[NBLK][NS];
     int32_t id[NBLK];
     int32_t hid[NBLK];
+    int32_t sim[NBLK];
     uint8_t flag[NBLK];
 };
 
-// st.id[] (-1 = none) must be written and synchronised before the call
-template <typename Lt, int NBLK>
-__device__ void stage_blocks(const DevMesh &m, BlockStage<Lt, NBLK> &st) {
+// st.id[] (-1 = none) must be written and synchronised before the call;
+// mesh_of(s) gives the mesh of entry s
+template <typename Lt, int NBLK, typename MeshOf>
+__device__ void stage_blocks_by(MeshOf mesh_of, BlockStage<Lt, NBLK> &st) {
     for (int e = threadIdx.x; e < NBLK * Lt::NB; e += blockDim.x) {
         const int s = e / Lt::NB, p = e - s * Lt::NB;
         const int B = st.id[s];
-        st.link[s][dir_region<Lt>(p)] = B >= 0 ? m.nbr[(int64_t)p * m.cap + B] : 0;
+        int32_t v = 0, h = -1;
+        uint8_t fl = 0;
+        if (B >= 0) {
+            const DevMesh &m = mesh_of(s);
+            v = m.nbr[(int64_t)p * m.cap + B];
+            if (p == 0) {
+                h = m.hid[B];
+                fl = m.bflag[B];
+            }
+        }
+        st.link[s][dir_region<Lt>(p)] = v;
         if (p == 0) {
-            st.hid[s] = B >= 0 ? m.hid[B] : -1;
-            st.flag[s] = B >= 0 ? m.bflag[B] : 0;
+            st.hid[s] = h;
+            st.flag[s] = fl;
         }
     }
     __syncthreads();
+}
+
+template <typename Lt, int NBLK>
+__device__ void stage_blocks(const DevMesh &m, BlockStage<Lt, NBLK> &st) {
+    stage_blocks_by<Lt, NBLK>([&](int) -> const DevMesh & { return m; }, st);
+}
+
+// Contiguous range of work units [u0, u1) of a persistent workgroup: the
+// count is read on the device, so one launch shape serves every mesh.
+__device__ inline void persistent_range(int units, int &u0, int &u1) {
+    const int G = gridDim.x;
+    const int wg = xcd_remap(blockIdx.x, G);
+    const int per = (units + G - 1) / G;
+    u0 = min(units, wg * per);
+    u1 = min(units, u0 + per);
+}
+
+// Read-only view of the batch descriptors in the constant address space: with
+// a wave-uniform index their fields come in through scalar loads.
+typedef const __attribute__((address_space(4))) SimDesc CSimDesc;
+__device__ inline CSimDesc *const_view(const SimDesc *p) { return (CSimDesc *)p; }
+
+__device__ inline DevMesh load_mesh(CSimDesc *cs) {
+    DevMesh m;
+    m.cap = cs->m.cap;
+    m.capc = cs->m.capc;
+    m.lmax = cs->m.lmax;
+    m.halo_base = cs->m.halo_base;
+    m.nh = cs->m.nh;
+    m.hid = cs->m.hid;
+    m.parent = cs->m.parent;
+    m.fresh = cs->m.fresh;
+    m.nbr = cs->m.nbr;
+    m.nbrc = cs->m.nbrc;
+    m.X = cs->m.X;
+    m.level = cs->m.level;
+    m.status = cs->m.status;
+    m.tag = cs->m.tag;
+    m.ldes = cs->m.ldes;
+    m.viol = cs->m.viol;
+    m.bflag = cs->m.bflag;
+    m.gmask = cs->m.gmask;
+    m.imask = cs->m.imask;
+    return m;
+}
+
+// Thread index hidden from loop-invariant code motion: inside a persistent
+// loop the per-cell index arithmetic is then redone per work unit instead of
+// being hoisted and kept live across the loop.
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// decode a batch work item into (simulation, block)
+__device__ inline void decode_item(uint32_t it, int &sim, int &B) {
+    sim = (int)(it >> kItemSimShift);
+    B = (int)(it & kItemBlockMask);
 }
 
 // ---------------------------------------------------------------------------
@@ -165,22 +239,15 @@ __device__ void stage_blocks(const DevMesh &m, BlockStage<Lt, NBLK> &st) {
 // leave the fluid is replaced there by its bounce-back.  A population arriving
 // from a region covered only by a coarser block keeps the cell's own
 // post-collision value (halo record).
-template <int Q, int S>
-__global__ __launch_bounds__(256) void k_collide_stream(const int32_t *__restrict__ list, int n, DevMesh m,
-                                                        const typename Store<S>::T *__restrict__ src,
-                                                        typename Store<S>::T *__restrict__ dst, double omega_d,
-                                                        BCParams bc) {
+// Body: the cells of staged block s (this thread: cell l).
+template <int Q, int S, int NBLK>
+__device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage<Lat<Q>, NBLK> &st, int s, int l,
+                                              const typename Store<S>::T *__restrict__ src,
+                                              typename Store<S>::T *__restrict__ dst, typename Store<S>::R om,
+                                              const BCParams &bc) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
-    constexpr int MB = Lt::MB, BPW = 256 / MB;
-    __shared__ BlockStage<Lt, BPW> st;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int base = wg * BPW;
-    if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
-    __syncthreads();
-    stage_blocks<Lt, BPW>(m, st);
-    const int s = threadIdx.x / MB, l = threadIdx.x % MB;
     const int B = st.id[s];
     if (B < 0) return;
     const uint8_t flag = st.flag[s];
@@ -190,7 +257,6 @@ __global__ __launch_bounds__(256) void k_collide_stream(const int32_t *__restric
 
     R g[Q];
     R drho, ux, uy, uz;
-    const R om = R(omega_d);
     if constexpr (Lt::D == 3) {
         // Interior block (every region link a same-level block): one block per
         // wave, so the links are wave-uniform and every source is a select.
@@ -250,6 +316,61 @@ __global__ __launch_bounds__(256) void k_collide_stream(const int32_t *__restric
     }
 }
 
+template <int Q, int S>
+__global__ __launch_bounds__(256) void k_collide_stream(const int32_t *__restrict__ list, int n, DevMesh m,
+                                                        const typename Store<S>::T *__restrict__ src,
+                                                        typename Store<S>::T *__restrict__ dst, double omega_d,
+                                                        BCParams bc) {
+    using Lt = Lat<Q>;
+    using R = typename Store<S>::R;
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int base = wg * BPW;
+    if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
+    __syncthreads();
+    stage_blocks<Lt, BPW>(m, st);
+    collide_block<Q, S, BPW>(m, st, threadIdx.x / MB, threadIdx.x % MB, src, dst, R(omega_d), bc);
+}
+
+// Batched form: level L of every simulation of a batch in one persistent
+// launch of NT-thread workgroups (NT / Mb blocks each); all simulations share
+// the buffer parity `par` of level L.
+template <int Q, int S, int NT>
+__global__ __launch_bounds__(NT) void k_collide_stream_batch(const SimDesc *__restrict__ sims,
+                                                             const uint32_t *__restrict__ items,
+                                                             const int32_t *__restrict__ count, int L, int par) {
+    using Lt = Lat<Q>;
+    using ST = Store<S>;
+    using R = typename ST::R;
+    using T = typename ST::T;
+    constexpr int MB = Lt::MB, BPW = NT / MB;
+    __shared__ BlockStage<Lt, BPW> st;
+    const int n = *count;
+    int u0, u1;
+    persistent_range((n + BPW - 1) / BPW, u0, u1);
+    for (int u = u0; u < u1; u++) {
+        if ((int)threadIdx.x < BPW) {
+            const int idx = u * BPW + (int)threadIdx.x;
+            int sim = 0, B = -1;
+            if (idx < n) decode_item(items[idx], sim, B);
+            st.id[threadIdx.x] = B;
+            st.sim[threadIdx.x] = sim;
+        }
+        __syncthreads();
+        stage_blocks_by<Lt, BPW>([&](int e) -> const DevMesh & { return sims[st.sim[e]].m; }, st);
+        const int tid = opaque_tid();
+        const int s = tid / MB;
+        int sim = st.sim[s];
+        if (MB == 64) sim = __builtin_amdgcn_readfirstlane(sim);  // one block per wave
+        CSimDesc *cs = const_view(sims) + sim;
+        const DevMesh m = load_mesh(cs);
+        collide_block<Q, S, BPW>(m, st, s, tid % MB, (const T *)cs->f[par], (T *)cs->f[1 - par],
+                                 R(cs->lp.omega[L]), sims[sim].bc);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Coarse-to-fine linear interpolation with Dupuis-Chopard rescaling (Sec.
 // "Linear Interpolation").  One parent block per workgroup: its cells are
@@ -274,66 +395,108 @@ __device__ inline R lin3(const R *F, R x, R y, R z) {
     return a0 + a1 * x + a2 * y + a3 * z + a4 * x * y + a5 * y * z + a6 * x * z + a7 * x * y * z;
 }
 
+template <typename Lt, typename R>
+struct InterpSmem {
+    R g[Lt::Q][Lt::MB];
+    uint64_t gm[Lt::NC];
+    BlockStage<Lt, Lt::NC + 1> st;  // entry NC = the parent
+};
+
+// Body (whole workgroup): targeted cells of the children of refined parent P.
 template <int Q, int S>
-__global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list, int n, DevMesh m,
-                                                typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
-                                                int all_cells) {
+__device__ __forceinline__ void interp_parent(const DevMesh &m, int P, const typename Store<S>::T *src,
+                                              typename Store<S>::T *dst, typename Store<S>::R r, int all_cells,
+                                              InterpSmem<Lat<Q>, typename Store<S>::R> &sm, int t) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
-    using T = typename ST::T;
     constexpr int MB = Lt::MB, NC = Lt::NC;
-    __shared__ R s_g[Q][MB];
-    __shared__ uint64_t s_gm[NC];
-    __shared__ BlockStage<Lt, NC + 1> st;  // entry NC = the parent
-    if ((int)blockIdx.x >= n) return;
-    const int P = list[blockIdx.x];
-    const int L = m.level[P];
     const int first = m.nbrc[P];
-    if (first < 0 || first > m.cap - NC || L + 1 >= m.lmax) return;  // only refined parents are listed
-    const T *src = lp.par[L] ? f1 : f0;
-    T *dst = lp.par[L + 1] ? f1 : f0;
-    const R r = R(lp.r_cf[L]);
-    const int t = threadIdx.x;
-    if (t <= NC) st.id[t] = t < NC ? first + t : P;
-    if (t < NC) s_gm[t] = all_cells ? ~0ull : m.gmask[first + t];
+    if (t <= NC) sm.st.id[t] = t < NC ? first + t : P;
+    if (t < NC) sm.gm[t] = all_cells ? ~0ull : m.gmask[first + t];
     __syncthreads();
-    stage_blocks<Lt, NC + 1>(m, st);
+    stage_blocks<Lt, NC + 1>(m, sm.st);
     if (t < MB) {
         R g[Q];
-        gather_cell<Lt, ST>(m, st.link[NC], P, st.hid[NC], t, src, g);
+        gather_cell<Lt, ST>(m, sm.st.link[NC], P, sm.st.hid[NC], t, src, g);
         R drho, ux, uy, uz;
         moments_g<Lt, R>(g, drho, ux, uy, uz);
         const R uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
         for (int p = 0; p < Q; p++) {
             const R ge = geq<Lt, R>(p, drho, ux, uy, uz, uu);
-            s_g[p][t] = ge + r * (g[p] - ge);
+            sm.g[p][t] = ge + r * (g[p] - ge);
         }
     }
     __syncthreads();
     for (int e = t; e < NC * MB; e += blockDim.x) {
         const int c = e / MB, lf = e - c * MB;
-        if (!((s_gm[c] >> lf) & 1ull)) continue;
+        if (!((sm.gm[c] >> lf) & 1ull)) continue;
         const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
         const int I = lf & 3, J = (lf >> 2) & 3, K = lf >> 4;
         const R x = R(-0.25) + R(0.5) * R(I), y = R(-0.25) + R(0.5) * R(J), z = R(-0.25) + R(0.5) * R(K);
         const int m0 = 2 * cx + 4 * (2 * cy) + 16 * (2 * cz);
-        const int32_t *link = st.link[c];
-        const int hc = st.hid[c];
+        const int32_t *link = sm.st.link[c];
+        const int hc = sm.st.hid[c];
 #pragma unroll
         for (int p = 0; p < Q; p++) {
             R v;
             if (Lt::D == 2) {
-                v = lin2<R>(s_g[p][m0], s_g[p][m0 + 1], s_g[p][m0 + 4], s_g[p][m0 + 5], x, y);
+                v = lin2<R>(sm.g[p][m0], sm.g[p][m0 + 1], sm.g[p][m0 + 4], sm.g[p][m0 + 5], x, y);
             } else {
                 R F[8];
 #pragma unroll
-                for (int nn = 0; nn < 8; nn++) F[nn] = s_g[p][m0 + (nn & 1) + 4 * ((nn >> 1) & 1) + 16 * (nn >> 2)];
+                for (int nn = 0; nn < 8; nn++) F[nn] = sm.g[p][m0 + (nn & 1) + 4 * ((nn >> 1) & 1) + 16 * (nn >> 2)];
                 v = lin3<R>(F, x, y, z);
             }
             store_g<Lt, ST>(dst, entry_slot<Lt>(m, link, first + c, hc, p, lf), p, v);
         }
+    }
+}
+
+// refined parents only (a listed block that is not one is skipped)
+__device__ inline bool interp_target(const DevMesh &m, int P, int nc) {
+    const int first = m.nbrc[P];
+    return !(first < 0 || first > m.cap - nc || m.level[P] + 1 >= m.lmax);
+}
+
+template <int Q, int S>
+__global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list, int n, DevMesh m,
+                                                typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
+                                                int all_cells) {
+    using R = typename Store<S>::R;
+    __shared__ InterpSmem<Lat<Q>, R> sm;
+    if ((int)blockIdx.x >= n) return;
+    const int P = list[blockIdx.x];
+    if (!interp_target(m, P, Lat<Q>::NC)) return;
+    const int L = m.level[P];
+    interp_parent<Q, S>(m, P, lp.par[L] ? f1 : f0, lp.par[L + 1] ? f1 : f0, R(lp.r_cf[L]), all_cells, sm,
+                        threadIdx.x);
+}
+
+// Batched ghost fill of level L+1 from level L (interface parents of every
+// simulation), persistent workgroups; par0/par1 = buffers of levels L, L+1.
+template <int Q, int S>
+__global__ __launch_bounds__(256) void k_interp_batch(const SimDesc *__restrict__ sims,
+                                                      const uint32_t *__restrict__ items,
+                                                      const int32_t *__restrict__ count, int L, int par0, int par1) {
+    using ST = Store<S>;
+    using R = typename ST::R;
+    using T = typename ST::T;
+    __shared__ InterpSmem<Lat<Q>, R> sm;
+    int u0, u1;
+    persistent_range(*count, u0, u1);
+    for (int u = u0; u < u1; u++) {
+        int sim, P;
+        decode_item(items[u], sim, P);
+        sim = __builtin_amdgcn_readfirstlane(sim);  // one item per workgroup
+        P = __builtin_amdgcn_readfirstlane(P);
+        CSimDesc *cs = const_view(sims) + sim;
+        const DevMesh m = load_mesh(cs);
+        if (interp_target(m, P, Lat<Q>::NC))
+            interp_parent<Q, S>(m, P, (const T *)cs->f[par0], (T *)cs->f[par1], R(cs->lp.r_cf[L]), 0, sm,
+                                opaque_tid());
+        __syncthreads();
     }
 }
 
@@ -440,43 +603,29 @@ __global__ void k_clear_fresh(const int32_t *__restrict__ list, int n, DevMesh m
 // (i,j,k) takes the mean of the 2^d rescaled cells of child octant
 // (i/2, j/2, k/2) starting at fine cell (2(i mod 2), 2(j mod 2), 2(k mod 2)).
 // One thread per parent cell; 64-thread workgroups (one 3-D parent, four 2-D).
-template <int Q, int S>
-__global__ __launch_bounds__(64) void k_average(const int32_t *__restrict__ list, int n, DevMesh m,
-                                                typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
-                                                int all_cells) {
+// Staging entry of child c (c = NC: the parent itself) of listed parent P,
+// -1 if P is not a refined block with children in the next level.
+__device__ inline int average_entry(const DevMesh &m, int P, int c, int nc) {
+    const int c0 = m.nbrc[P];
+    const bool ok = is_refined(m.status[P]) && c0 >= 0 && c0 <= m.cap - nc && m.level[P] + 1 < m.lmax;
+    return ok ? (c < nc ? c0 + c : P) : -1;
+}
+
+// Body: parent cell l of the parent staged at entries sb .. sb+NC.
+template <int Q, int S, int NS>
+__device__ __forceinline__ void average_cell(const DevMesh &m, const BlockStage<Lat<Q>, NS> &st, int sb, int l,
+                                             const typename Store<S>::T *src, typename Store<S>::T *dst,
+                                             typename Store<S>::R r, int all_cells) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
-    using T = typename ST::T;
-    constexpr int MB = Lt::MB, NC = Lt::NC, PPW = 64 / MB;
-    __shared__ BlockStage<Lt, PPW * (NC + 1)> st;  // per parent: NC children, then the parent
-    const int s = threadIdx.x / MB, l = threadIdx.x % MB;
-    if ((int)threadIdx.x < PPW * (NC + 1)) {
-        const int ps = threadIdx.x / (NC + 1), c = threadIdx.x - ps * (NC + 1);
-        const int idx = blockIdx.x * PPW + ps;
-        int id = -1;
-        if (idx < n) {
-            const int P = list[idx];
-            const int c0 = m.nbrc[P];
-            const bool ok = is_refined(m.status[P]) && c0 >= 0 && c0 <= m.cap - NC && m.level[P] + 1 < m.lmax;
-            if (ok) id = c < NC ? c0 + c : P;
-        }
-        st.id[threadIdx.x] = id;
-    }
-    __syncthreads();
-    stage_blocks<Lt, PPW * (NC + 1)>(m, st);
-    const int sb = s * (NC + 1);
+    constexpr int NC = Lt::NC;
     const int P = st.id[sb + NC];
-    if (P < 0) return;
-    const int L = m.level[P];
     const int i = l & 3, j = (l >> 2) & 3, k = l >> 4;
     const int c = (i >> 1) + 2 * (j >> 1) + 4 * (k >> 1);
     const int child = st.id[sb + c];
     const int fb = 2 * (i & 1) + 8 * (j & 1) + 32 * (k & 1);
     if (!all_cells && !((m.imask[child] >> fb) & 1ull)) return;
-    const T *src = lp.par[L + 1] ? f1 : f0;
-    T *dst = lp.par[L] ? f1 : f0;
-    const R r = R(lp.r_fc[L]);
     // mean of the rescaled fine cells, sum_n [geq_n + r (g_n - geq_n)] / N_c,
     // evaluated as ((1 - r) sum_n geq_n + r sum_n g_n) / N_c so that only the
     // populations' sum and each fine cell's moments stay live
@@ -514,6 +663,100 @@ __global__ __launch_bounds__(64) void k_average(const int32_t *__restrict__ list
         const R v = ((R(1) - r) * se[p] + r * acc[p]) / R(NC);
         store_g<Lt, ST>(dst, entry_slot<Lt>(m, plink, P, ph, p, l), p, v);
     }
+}
+
+template <int Q, int S>
+__global__ __launch_bounds__(64) void k_average(const int32_t *__restrict__ list, int n, DevMesh m,
+                                                typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
+                                                int all_cells) {
+    using Lt = Lat<Q>;
+    using R = typename Store<S>::R;
+    constexpr int MB = Lt::MB, NC = Lt::NC, PPW = 64 / MB;
+    __shared__ BlockStage<Lt, PPW * (NC + 1)> st;  // per parent: NC children, then the parent
+    if ((int)threadIdx.x < PPW * (NC + 1)) {
+        const int ps = threadIdx.x / (NC + 1), c = threadIdx.x - ps * (NC + 1);
+        const int idx = blockIdx.x * PPW + ps;
+        st.id[threadIdx.x] = idx < n ? average_entry(m, list[idx], c, NC) : -1;
+    }
+    __syncthreads();
+    stage_blocks<Lt, PPW * (NC + 1)>(m, st);
+    const int s = threadIdx.x / MB, sb = s * (NC + 1);
+    const int P = st.id[sb + NC];
+    if (P < 0) return;
+    const int L = m.level[P];
+    average_cell<Q, S, PPW * (NC + 1)>(m, st, sb, threadIdx.x % MB, lp.par[L + 1] ? f1 : f0, lp.par[L] ? f1 : f0,
+                                       R(lp.r_fc[L]), all_cells);
+}
+
+// Batched interface averaging of level L+1 into level L, persistent 64-thread
+// workgroups; par0/par1 = buffers of levels L, L+1.
+template <int Q, int S>
+__global__ __launch_bounds__(64) void k_average_batch(const SimDesc *__restrict__ sims,
+                                                      const uint32_t *__restrict__ items,
+                                                      const int32_t *__restrict__ count, int L, int par0, int par1) {
+    using Lt = Lat<Q>;
+    using ST = Store<S>;
+    using R = typename ST::R;
+    using T = typename ST::T;
+    constexpr int MB = Lt::MB, NC = Lt::NC, PPW = 64 / MB, NS = PPW * (NC + 1);
+    __shared__ BlockStage<Lt, NS> st;
+    const int n = *count;
+    int u0, u1;
+    persistent_range((n + PPW - 1) / PPW, u0, u1);
+    for (int u = u0; u < u1; u++) {
+        if ((int)threadIdx.x < NS) {
+            const int ps = threadIdx.x / (NC + 1), c = threadIdx.x - ps * (NC + 1);
+            const int idx = u * PPW + ps;
+            int sim = 0, P = -1, id = -1;
+            if (idx < n) {
+                decode_item(items[idx], sim, P);
+                id = average_entry(sims[sim].m, P, c, NC);
+            }
+            st.id[threadIdx.x] = id;
+            st.sim[threadIdx.x] = sim;
+        }
+        __syncthreads();
+        stage_blocks_by<Lt, NS>([&](int e) -> const DevMesh & { return sims[st.sim[e]].m; }, st);
+        const int tid = opaque_tid();
+        const int s = tid / MB, sb = s * (NC + 1);
+        if (st.id[sb + NC] >= 0) {
+            int sim = st.sim[sb + NC];
+            if (MB == 64) sim = __builtin_amdgcn_readfirstlane(sim);  // one parent per wave
+            CSimDesc *cs = const_view(sims) + sim;
+            const DevMesh m = load_mesh(cs);
+            average_cell<Q, S, NS>(m, st, sb, tid % MB, (const T *)cs->f[par1], (T *)cs->f[par0],
+                                   R(cs->lp.r_fc[L]), 0);
+        }
+        __syncthreads();
+    }
+}
+
+// Work items of a batch for every level: kind 0 = launch order of the level,
+// kind 1 = its interface parents; simulations in batch order.  Grid: x chunks
+// of a list, y = simulation, z = 2 * level + kind.  counts[2 L + kind].
+__global__ void k_batch_items(const SimDesc *__restrict__ sims, int nsims, uint32_t *__restrict__ items,
+                              int64_t stride, int32_t *__restrict__ counts) {
+    const int s = blockIdx.y, L = blockIdx.z >> 1, kind = blockIdx.z & 1;
+    __shared__ int s_off, s_n;
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int t = 0; t < s; t++) {
+            const SimDesc &o = sims[t];
+            if (L < o.m.lmax) off += kind == 0 ? o.nids[L] : o.niface[L];
+        }
+        const SimDesc &sd = sims[s];
+        const int n = L < sd.m.lmax ? (kind == 0 ? sd.nids[L] : sd.niface[L]) : 0;
+        s_off = off;
+        s_n = n;
+        if (s == nsims - 1 && blockIdx.x == 0) counts[blockIdx.z] = off + n;
+    }
+    __syncthreads();
+    const SimDesc &sd = sims[s];
+    const int32_t *src = (kind == 0 ? sd.order : sd.iface) + (int64_t)L * sd.m.cap;
+    uint32_t *dst = items + (int64_t)blockIdx.z * stride + s_off;
+    const uint32_t tag = (uint32_t)s << kItemSimShift;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s_n; i += gridDim.x * blockDim.x)
+        dst[i] = tag | (uint32_t)src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -860,6 +1103,42 @@ void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &
     AMR_DISPATCH(c.q, c.storage,
                  (k_interp<Qc, Sc><<<n, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]),
                                                                  lp, all_cells)));
+}
+
+template <int Q, int S>
+static void collide_batch_shape(hipStream_t stream, const SimDesc *sims, const uint32_t *items, const int32_t *count,
+                                int L, int par, int nt, int grid) {
+    if (nt == 64)
+        k_collide_stream_batch<Q, S, 64><<<grid, 64, 0, stream>>>(sims, items, count, L, par);
+    else if (nt == 128)
+        k_collide_stream_batch<Q, S, 128><<<grid, 128, 0, stream>>>(sims, items, count, L, par);
+    else
+        k_collide_stream_batch<Q, S, 256><<<grid, 256, 0, stream>>>(sims, items, count, L, par);
+}
+
+void launch_collide_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
+                          const int32_t *count, int L, int par, int nt, int grid) {
+    AMR_DISPATCH(q, storage, (collide_batch_shape<Qc, Sc>(stream, sims, items, count, L, par, nt, grid)));
+}
+
+void launch_interp_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
+                         const int32_t *count, int L, int par0, int par1, int grid) {
+    const int threads = q == 9 ? 64 : 256;
+    AMR_DISPATCH(q, storage,
+                 (k_interp_batch<Qc, Sc><<<grid, threads, 0, stream>>>(sims, items, count, L, par0, par1)));
+}
+
+void launch_average_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
+                          const int32_t *count, int L, int par0, int par1, int grid) {
+    AMR_DISPATCH(q, storage,
+                 (k_average_batch<Qc, Sc><<<grid, 64, 0, stream>>>(sims, items, count, L, par0, par1)));
+}
+
+void launch_batch_items(hipStream_t stream, const SimDesc *sims, int nsims, int lmax, int cap_max, uint32_t *items,
+                        int64_t stride, int32_t *counts) {
+    if (nsims <= 0 || lmax <= 0) return;
+    const int chunks = std::min(64, (cap_max + 255) / 256);
+    k_batch_items<<<dim3(chunks, nsims, 2 * lmax), 256, 0, stream>>>(sims, nsims, items, stride, counts);
 }
 
 void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const LevelParams &lp) {

@@ -10,13 +10,15 @@
 #include <utility>
 #include <vector>
 
-#include "kernels.h"
+#include "runtime_internal.h"
 
 using namespace amr;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace amr {
 
 amr_status fail(amr_status code, const char *fmt, ...) {
     char buf[512];
@@ -28,19 +30,20 @@ amr_status fail(amr_status code, const char *fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) return fail(AMR_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+LevelParams level_params(const amr_handle *h) {
+    LevelParams lp;
+    for (int L = 0; L < kMaxLevels; L++) {
+        lp.par[L] = L < h->lmax ? h->par[L] : 0;
+        lp.omega[L] = L < h->lmax ? 1.0 / h->tau[L] : 0.0;
+        lp.r_cf[L] = L + 1 < h->lmax ? h->tau[L + 1] / (2.0 * h->tau[L]) : 0.0;
+        lp.r_fc[L] = L + 1 < h->lmax ? 2.0 * h->tau[L] / h->tau[L + 1] : 0.0;
+    }
+    return lp;
+}
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace amr
 
-struct Layout {
-    size_t f[2], nbr, nbrc, X, level, status, tag, ldes, viol, bflag, gmask, imask;
-    size_t ids, ids_tmp, iface, order, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
-    size_t crit, part4, solid, solid_list, ctr, staging, staging_bytes, total, hid, U, parent, fresh;
-};
+namespace {
 
 int nroot_of(const amr_config *c) { return c->root[0] * c->root[1] * (c->dim == 3 ? c->root[2] : 1); }
 
@@ -120,42 +123,6 @@ void make_layout(const amr_config *c, Layout *L) {
     L->total = align256(t);
 }
 
-}  // namespace
-
-struct amr_handle {
-    amr_config cfg;
-    Ctx c;
-    Layout lay;
-    int lmax;
-    int nids[kMaxLevels], niface[kMaxLevels];
-    int gtop;
-    int par[kMaxLevels];
-    double tau[kMaxLevels];
-    BCParams bc;
-    std::vector<uint8_t> solid;
-    // graph of one coarse step, per level-0 parity
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    bool graph_ok = false;
-    // AMR_PROFILE: events around each solver launch (kind, start, stop, blocks, bytes)
-    bool profiling = false;
-    struct Timed { int kind; hipEvent_t a, b; double blocks, bytes; };
-    std::vector<Timed> timed;
-    std::vector<hipEvent_t> event_pool;
-    double kstats[3][4] = {{0}};
-};
-
-namespace {
-
-LevelParams level_params(const amr_handle *h) {
-    LevelParams lp;
-    for (int L = 0; L < kMaxLevels; L++) {
-        lp.par[L] = L < h->lmax ? h->par[L] : 0;
-        lp.omega[L] = L < h->lmax ? 1.0 / h->tau[L] : 0.0;
-        lp.r_cf[L] = L + 1 < h->lmax ? h->tau[L + 1] / (2.0 * h->tau[L]) : 0.0;
-        lp.r_fc[L] = L + 1 < h->lmax ? 2.0 * h->tau[L] / h->tau[L + 1] : 0.0;
-    }
-    return lp;
-}
 
 hipEvent_t take_event(amr_handle *h) {
     if (!h->event_pool.empty()) {

@@ -1,0 +1,62 @@
+// runtime_internal.h -- state shared by the host runtime files (single
+// simulations in runtime.hip, batches in batch.hip): the handle behind amr_t,
+// its arena layout, error reporting.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/amr_lbm.h"
+#include "kernels.h"
+
+namespace amr {
+
+// record a message for amr_last_error() and return `code`
+amr_status fail(amr_status code, const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(AMR_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t f[2], nbr, nbrc, X, level, status, tag, ldes, viol, bflag, gmask, imask;
+    size_t ids, ids_tmp, iface, order, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
+    size_t crit, part4, solid, solid_list, ctr, staging, staging_bytes, total, hid, U, parent, fresh;
+};
+
+}  // namespace amr
+
+using namespace amr;
+
+struct amr_handle {
+    amr_config cfg;
+    Ctx c;
+    Layout lay;
+    int lmax;
+    int nids[kMaxLevels], niface[kMaxLevels];
+    int gtop;
+    int par[kMaxLevels];
+    double tau[kMaxLevels];
+    BCParams bc;
+    std::vector<uint8_t> solid;
+    // graph of one coarse step, per level-0 parity
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool graph_ok = false;
+    // AMR_PROFILE: events around each solver launch (kind, start, stop, blocks, bytes)
+    bool profiling = false;
+    struct Timed { int kind; hipEvent_t a, b; double blocks, bytes; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+    double kstats[3][4] = {{0}};
+};
+
+namespace amr {
+
+// relaxation and rescaling of every level, with the current buffer parities
+LevelParams level_params(const amr_handle *h);
+
+}  // namespace amr
