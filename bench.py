@@ -102,6 +102,103 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
     return out
 
 
+def run_batch(steps, warmup, theta, trial_steps=2):
+    """the batched set-up: 64 cavities advanced by fused level sweeps"""
+    import torch
+    from paper_2308_08085_amd import abi, workloads as W
+
+    cases = W.config5_cases()
+    stream = torch.cuda.Stream()
+    sims = []
+    for c in cases:
+        g = abi.AmrLbm(c, stream=stream)
+        g.set_root_rho_u(c.initial_rho_u())
+        sims.append(g)
+    b = abi.AmrBatch(sims)
+    best, best_ms = b.autotune(trial_steps=trial_steps)
+    log("[batch] %d simulations, autotuned shape %s (%.3f ms per coarse step)" % (len(sims), best, best_ms))
+    period = cases[0].adapt_every
+    live = [True] * len(sims)
+    refused = [0]
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+
+    def updates():
+        return [period * W.mlups_updates(g.counts(), c.dim) for g, c in zip(sims, cases)]
+
+    def one_period():
+        u = updates()
+        ev0.record(stream)
+        b.step(period, graph=True)
+        ev1.record(stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for i, g in enumerate(sims):
+            if not live[i]:
+                continue
+            if not np.all(np.isfinite(g.mass_mom())):
+                live[i] = False
+                continue
+            g.tag(abi.TAG_VORTICITY_REL, theta=theta)
+            try:
+                g.adapt()
+            except abi.AmrError as e:  # atomic refusal: the mesh is unchanged
+                if e.code != abi.AMR_ERR_CAPACITY:
+                    raise
+                refused[0] += 1
+        t_adapt = time.perf_counter() - t0
+        return sum(x for x, ok in zip(u, live) if ok), ev0.elapsed_time(ev1), t_adapt * 1e3
+
+    for i in range(warmup):
+        u, ms, ams = one_period()
+        log("[batch] warmup %d/%d: %.1f MLUPS, adapt %.1f ms (all members)" % (i + 1, warmup, u / ms / 1e3, ams))
+    tot_u = tot_ms = tot_a = 0.0
+    for i in range(steps):
+        u, ms, ams = one_period()
+        tot_u += u
+        tot_ms += ms
+        tot_a += ams
+    # the same members one after another, each replaying its own graph
+    u = updates()
+    for g in sims:  # capture outside the timed region
+        g.step(2, graph=True)
+    b.step(0)
+    ev0.record(stream)
+    for g in sims:
+        g.step(period, graph=True)
+    ev1.record(stream)
+    stream.synchronize()
+    seq_ms = ev0.elapsed_time(ev1)
+    seq_mlups = sum(x for x, ok in zip(u, live) if ok) / seq_ms / 1e3
+    mlups = tot_u / tot_ms / 1e3
+    unstable = [cases[i].name for i in range(len(sims)) if not live[i]]
+    log("[batch] timed %d periods: %.1f MLUPS fused vs %.1f one by one; %d members non-finite" %
+        (steps, mlups, seq_mlups, len(unstable)))
+    out = {"workload": "64 lid-driven cavities (32 D2Q9 sides 32-256, 32 D3Q19 sides 32-64), Re log-uniform "
+                       "100-3200, 2-4 levels, FP16 shifted storage, adaptation every 50 coarse steps",
+           "mlups": round(mlups, 1), "mlups_members_one_by_one": round(seq_mlups, 1),
+           "speedup_vs_one_by_one": round(mlups / seq_mlups, 3),
+           "adapt_ms_per_cycle_all_members": round(tot_a / steps, 2),
+           "tuning": best, "non_finite_members": unstable, "adaptations_refused_for_capacity": refused[0],
+           "blocks": int(sum(int(g.counts().sum()) for g in sims))}
+    b.close()
+    for g in sims:
+        g.close()
+    del b, sims
+    torch.cuda.empty_cache()
+    return out
+
+
+def kernel_rates(res):
+    """event-timed rate of each solver kernel over the profiled periods"""
+    out = {}
+    for k, v in res["kernels"].items():
+        if v["launches"] and v["ms"] > 0:
+            out[k] = {"launches": v["launches"], "avg_us": round(v["ms"] * 1e3 / v["launches"], 2),
+                      "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)}
+    return out
+
+
 def roofline(res, kernel):
     k = res["kernels"]["collide_stream"]
     gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
@@ -190,7 +287,19 @@ def main():
     ap.add_argument("--no-error-leg", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-cavity", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device-to-device three times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 3}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
@@ -206,6 +315,7 @@ def main():
     r16 = None if args.no_fp16 else run_storage(main_case, "f16s", args.steps, args.warmup, theta)
     c32 = None if args.no_cavity else run_storage(cav, "f32s", args.steps, args.warmup, theta)
     c16 = None if (args.no_cavity or args.no_fp16) else run_storage(cav, "f16s", args.steps, args.warmup, theta)
+    bat = None if args.no_batch else run_batch(max(2, args.steps // 2), 2, theta)
     err = None if args.no_error_leg else error_leg(theta)
     cpu = None if args.no_cpu_baseline else cpu_baseline(theta)
     line = {
@@ -231,6 +341,7 @@ def main():
         "adapt_ms_per_cycle": round(r32["adapt_ms_per_cycle"], 3),
         "mlups_incl_adapt": round(r32["mlups_wall"], 1),
         "roofline": roofline(r32, "k_collide_stream<27, F32S>"),
+        "kernels_f32s": kernel_rates(r32),
         "cpu_baseline": cpu,
     }
     if r16 is not None:
@@ -246,6 +357,8 @@ def main():
         if c16 is not None:
             line["cavity_d3q19"]["mlups_f16s"] = round(c16["mlups"], 1)
             line["cavity_d3q19"]["speedup_f16s_vs_f32s"] = round(c16["mlups"] / c32["mlups"], 3)
+    if bat is not None:
+        line["batched_cfg5"] = bat
     if err is not None:
         line["error_vs_fp64_oracle"] = err
     print(json.dumps(line), flush=True)

@@ -172,7 +172,8 @@ def config5_cases(n: int = 64, seed: int = 2308090):
             dim, q, side = 3, 19, int(rng.choice([32, 48, 64]))
         re = float(math.exp(rng.uniform(math.log(100.0), math.log(3200.0))))
         lmax = int(rng.integers(2, 5))
-        out.append(cavity(dim, q, side, lmax, re, storage="f16s", seed=seed + 1 + s,
+        nroot = (side // 4) ** dim
+        out.append(cavity(dim, q, side, lmax, re, storage="f16s", seed=seed + 1 + s, cap=nroot * 48,
                           name="cfg5_sim%02d" % s, steps=1000, adapt_every=50))
     return out
 
