@@ -34,6 +34,12 @@ if HERE not in sys.path:
 
 METRIC = "AMR-LBM MLUPS (FP32 vs FP16-storage) + adapt ms/cycle; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the dominant kernel on the main workload, from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, per
+# dispatch), each scaled by what the counter reads for a 1 GiB copy
+# (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Must be measured
+# again whenever the kernel changes.
+MEASURED_TRAFFIC = {"k_collide_stream<27, F32S>": (1921123 * 2.0 + 3050052 * 1.0) * 1024}
 
 
 def log(*a):
@@ -202,8 +208,10 @@ def kernel_rates(res):
 def roofline(res, kernel):
     k = res["kernels"]["collide_stream"]
     gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+    traffic = MEASURED_TRAFFIC.get(kernel)
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic) if traffic else None,
+            "traffic_over_algorithmic": round(traffic * max(k["launches"], 1) / k["bytes"], 3) if traffic else None,
             "kernel": kernel,
             "avg_launch_us": round(k["ms"] * 1e3 / max(k["launches"], 1), 2),
             "bytes_per_launch": round(k["bytes"] / max(k["launches"], 1))}
