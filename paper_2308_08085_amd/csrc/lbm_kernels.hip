@@ -602,131 +602,101 @@ __global__ void k_clear_fresh(const int32_t *__restrict__ list, int n, DevMesh m
 // Fine-to-coarse averaging with rescaling (Sec. "Averaging"): parent cell
 // (i,j,k) takes the mean of the 2^d rescaled cells of child octant
 // (i/2, j/2, k/2) starting at fine cell (2(i mod 2), 2(j mod 2), 2(k mod 2)).
-// One thread per parent cell; 64-thread workgroups (one 3-D parent, four 2-D).
-// Staging entry of child c (c = NC: the parent itself) of listed parent P,
-// -1 if P is not a refined block with children in the next level.
-__device__ inline int average_entry(const DevMesh &m, int P, int c, int nc) {
+// One workgroup per parent, one lane per fine cell of its children (3-D: a
+// wave per child): every lane gathers and rescales its cell, the 2^d cells of
+// a parent cell (lanes differing in bits 0, 2, 4 of the cell index) are summed
+// with xor shuffles, and the lane of the first one writes the parent cell.
+// Children without a targeted cell are skipped whole.
+
+// refined parents with children in the next level
+__device__ inline bool average_target(const DevMesh &m, int P, int nc) {
     const int c0 = m.nbrc[P];
-    const bool ok = is_refined(m.status[P]) && c0 >= 0 && c0 <= m.cap - nc && m.level[P] + 1 < m.lmax;
-    return ok ? (c < nc ? c0 + c : P) : -1;
+    return is_refined(m.status[P]) && c0 >= 0 && c0 <= m.cap - nc && m.level[P] + 1 < m.lmax;
 }
 
-// Body: parent cell l of the parent staged at entries sb .. sb+NC.
-template <int Q, int S, int NS>
-__device__ __forceinline__ void average_cell(const DevMesh &m, const BlockStage<Lat<Q>, NS> &st, int sb, int l,
-                                             const typename Store<S>::T *src, typename Store<S>::T *dst,
-                                             typename Store<S>::R r, int all_cells) {
+template <typename R>
+__device__ __forceinline__ R xor_sum(R v, int mask) {
+    return v + __shfl_xor(v, mask, 64);
+}
+
+template <int Q, int S>
+__device__ __forceinline__ void average_parent(const DevMesh &m, int P, const typename Store<S>::T *src,
+                                               typename Store<S>::T *dst, typename Store<S>::R r, int all_cells,
+                                               BlockStage<Lat<Q>, Lat<Q>::NC + 1> &st, int t) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
-    constexpr int NC = Lt::NC;
-    const int P = st.id[sb + NC];
-    const int i = l & 3, j = (l >> 2) & 3, k = l >> 4;
-    const int c = (i >> 1) + 2 * (j >> 1) + 4 * (k >> 1);
-    const int child = st.id[sb + c];
-    const int fb = 2 * (i & 1) + 8 * (j & 1) + 32 * (k & 1);
-    if (!all_cells && !((m.imask[child] >> fb) & 1ull)) return;
-    // mean of the rescaled fine cells, sum_n [geq_n + r (g_n - geq_n)] / N_c,
-    // evaluated as ((1 - r) sum_n geq_n + r sum_n g_n) / N_c so that only the
-    // populations' sum and each fine cell's moments stay live
-    R acc[Q], se[Q];
+    constexpr int MB = Lt::MB, NC = Lt::NC;
+    const int first = m.nbrc[P];
+    if (t <= NC) st.id[t] = t < NC ? first + t : P;
+    __syncthreads();
+    stage_blocks<Lt, NC + 1>(m, st);
+    const int c = t / MB, lf = t - c * MB;
+    if (c >= NC) return;
+    const int child = first + c;
+    const uint64_t im = all_cells ? ~0ull : m.imask[child];
+    if (im == 0) return;  // the whole child (a wave in 3-D, a 16-lane group in 2-D)
+    R g[Q];
+    gather_cell<Lt, ST>(m, st.link[c], child, st.hid[c], lf, src, g);
+    R drho, ux, uy, uz;
+    moments_g<Lt, R>(g, drho, ux, uy, uz);
+    const R uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
     for (int p = 0; p < Q; p++) {
-        acc[p] = R(0);
-        se[p] = R(0);
+        const R ge = geq<Lt, R>(p, drho, ux, uy, uz, uu);
+        R v = ge + r * (g[p] - ge);
+        v = xor_sum(v, 1);
+        v = xor_sum(v, 4);
+        if (Lt::D == 3) v = xor_sum(v, 16);
+        g[p] = v;
     }
-    const int32_t *clink = st.link[sb + c];
-    const int ch = st.hid[sb + c];
-#pragma unroll 1
-    for (int nn = 0; nn < NC; nn++) {
-        const int lf = fb + (nn & 1) + 4 * ((nn >> 1) & 1) + 16 * (nn >> 2);
-        R d = 0, jx = 0, jy = 0, jz = 0;
+    const int i = lf & 3, j = (lf >> 2) & 3, k = lf >> 4;
+    if (((i | j | k) & 1) || !((im >> lf) & 1ull)) return;
+    const int l = ((c & 1) * 2 + (i >> 1)) + 4 * (((c >> 1) & 1) * 2 + (j >> 1)) + 16 * ((c >> 2) * 2 + (k >> 1));
+    const int32_t *plink = st.link[NC];
+    const int ph = st.hid[NC];
 #pragma unroll
-        for (int p = 0; p < Q; p++) {
-            const R gv = load_g<Lt, ST>(src, entry_slot<Lt>(m, clink, child, ch, p, lf), p);
-            acc[p] += gv;
-            d += gv;
-            if (Lt::cx(p) > 0) jx += gv; else if (Lt::cx(p) < 0) jx -= gv;
-            if (Lt::cy(p) > 0) jy += gv; else if (Lt::cy(p) < 0) jy -= gv;
-            if (Lt::cz(p) > 0) jz += gv; else if (Lt::cz(p) < 0) jz -= gv;
-        }
-        const R rho = R(1) + d;
-        const R ux = jx / rho, uy = jy / rho, uz = jz / rho;
-        const R uu = ux * ux + uy * uy + uz * uz;
-#pragma unroll
-        for (int p = 0; p < Q; p++) se[p] += geq<Lt, R>(p, d, ux, uy, uz, uu);
-    }
-    const int32_t *plink = st.link[sb + NC];
-    const int ph = st.hid[sb + NC];
-#pragma unroll
-    for (int p = 0; p < Q; p++) {
-        const R v = ((R(1) - r) * se[p] + r * acc[p]) / R(NC);
-        store_g<Lt, ST>(dst, entry_slot<Lt>(m, plink, P, ph, p, l), p, v);
-    }
+    for (int p = 0; p < Q; p++) store_g<Lt, ST>(dst, entry_slot<Lt>(m, plink, P, ph, p, l), p, g[p] / R(NC));
 }
 
 template <int Q, int S>
-__global__ __launch_bounds__(64) void k_average(const int32_t *__restrict__ list, int n, DevMesh m,
-                                                typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
-                                                int all_cells) {
+__global__ __launch_bounds__(512) void k_average(const int32_t *__restrict__ list, int n, DevMesh m,
+                                                 typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
+                                                 int all_cells) {
     using Lt = Lat<Q>;
     using R = typename Store<S>::R;
-    constexpr int MB = Lt::MB, NC = Lt::NC, PPW = 64 / MB;
-    __shared__ BlockStage<Lt, PPW * (NC + 1)> st;  // per parent: NC children, then the parent
-    if ((int)threadIdx.x < PPW * (NC + 1)) {
-        const int ps = threadIdx.x / (NC + 1), c = threadIdx.x - ps * (NC + 1);
-        const int idx = blockIdx.x * PPW + ps;
-        st.id[threadIdx.x] = idx < n ? average_entry(m, list[idx], c, NC) : -1;
-    }
-    __syncthreads();
-    stage_blocks<Lt, PPW * (NC + 1)>(m, st);
-    const int s = threadIdx.x / MB, sb = s * (NC + 1);
-    const int P = st.id[sb + NC];
-    if (P < 0) return;
+    __shared__ BlockStage<Lt, Lt::NC + 1> st;
+    if ((int)blockIdx.x >= n) return;
+    const int P = list[blockIdx.x];
+    if (!average_target(m, P, Lt::NC)) return;
     const int L = m.level[P];
-    average_cell<Q, S, PPW * (NC + 1)>(m, st, sb, threadIdx.x % MB, lp.par[L + 1] ? f1 : f0, lp.par[L] ? f1 : f0,
-                                       R(lp.r_fc[L]), all_cells);
+    average_parent<Q, S>(m, P, lp.par[L + 1] ? f1 : f0, lp.par[L] ? f1 : f0, R(lp.r_fc[L]), all_cells, st,
+                         threadIdx.x);
 }
 
-// Batched interface averaging of level L+1 into level L, persistent 64-thread
+// Batched interface averaging of level L+1 into level L, persistent
 // workgroups; par0/par1 = buffers of levels L, L+1.
 template <int Q, int S>
-__global__ __launch_bounds__(64) void k_average_batch(const SimDesc *__restrict__ sims,
-                                                      const uint32_t *__restrict__ items,
-                                                      const int32_t *__restrict__ count, int L, int par0, int par1) {
+__global__ __launch_bounds__(512) void k_average_batch(const SimDesc *__restrict__ sims,
+                                                       const uint32_t *__restrict__ items,
+                                                       const int32_t *__restrict__ count, int L, int par0, int par1) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
     using T = typename ST::T;
-    constexpr int MB = Lt::MB, NC = Lt::NC, PPW = 64 / MB, NS = PPW * (NC + 1);
-    __shared__ BlockStage<Lt, NS> st;
-    const int n = *count;
+    __shared__ BlockStage<Lt, Lt::NC + 1> st;
     int u0, u1;
-    persistent_range((n + PPW - 1) / PPW, u0, u1);
+    persistent_range(*count, u0, u1);
     for (int u = u0; u < u1; u++) {
-        if ((int)threadIdx.x < NS) {
-            const int ps = threadIdx.x / (NC + 1), c = threadIdx.x - ps * (NC + 1);
-            const int idx = u * PPW + ps;
-            int sim = 0, P = -1, id = -1;
-            if (idx < n) {
-                decode_item(items[idx], sim, P);
-                id = average_entry(sims[sim].m, P, c, NC);
-            }
-            st.id[threadIdx.x] = id;
-            st.sim[threadIdx.x] = sim;
-        }
-        __syncthreads();
-        stage_blocks_by<Lt, NS>([&](int e) -> const DevMesh & { return sims[st.sim[e]].m; }, st);
-        const int tid = opaque_tid();
-        const int s = tid / MB, sb = s * (NC + 1);
-        if (st.id[sb + NC] >= 0) {
-            int sim = st.sim[sb + NC];
-            if (MB == 64) sim = __builtin_amdgcn_readfirstlane(sim);  // one parent per wave
-            CSimDesc *cs = const_view(sims) + sim;
-            const DevMesh m = load_mesh(cs);
-            average_cell<Q, S, NS>(m, st, sb, tid % MB, (const T *)cs->f[par1], (T *)cs->f[par0],
-                                   R(cs->lp.r_fc[L]), 0);
-        }
+        int sim, P;
+        decode_item(items[u], sim, P);
+        sim = __builtin_amdgcn_readfirstlane(sim);  // one item per workgroup
+        P = __builtin_amdgcn_readfirstlane(P);
+        CSimDesc *cs = const_view(sims) + sim;
+        const DevMesh m = load_mesh(cs);
+        if (average_target(m, P, Lt::NC))
+            average_parent<Q, S>(m, P, (const T *)cs->f[par1], (T *)cs->f[par0], R(cs->lp.r_fc[L]), 0, st,
+                                 opaque_tid());
         __syncthreads();
     }
 }
@@ -1130,8 +1100,9 @@ void launch_interp_batch(hipStream_t stream, int q, int storage, const SimDesc *
 
 void launch_average_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
                           const int32_t *count, int L, int par0, int par1, int grid) {
+    const int threads = q == 9 ? 64 : 512;  // one lane per fine cell of the children
     AMR_DISPATCH(q, storage,
-                 (k_average_batch<Qc, Sc><<<grid, 64, 0, stream>>>(sims, items, count, L, par0, par1)));
+                 (k_average_batch<Qc, Sc><<<grid, threads, 0, stream>>>(sims, items, count, L, par0, par1)));
 }
 
 void launch_batch_items(hipStream_t stream, const SimDesc *sims, int nsims, int lmax, int cap_max, uint32_t *items,
@@ -1152,11 +1123,10 @@ void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const L
 
 void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {
     if (n <= 0) return;
-    const int ppw = 64 / c.mb;
-    const int grid = (n + ppw - 1) / ppw;
+    const int threads = c.nc * c.mb;  // one lane per fine cell of the children
     AMR_DISPATCH(c.q, c.storage,
-                 (k_average<Qc, Sc><<<grid, 64, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]),
-                                                               lp, all_cells)));
+                 (k_average<Qc, Sc><<<n, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]),
+                                                                 lp, all_cells)));
 }
 
 void launch_fill_rest(const Ctx &c) {
