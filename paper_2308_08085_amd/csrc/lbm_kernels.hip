@@ -316,14 +316,20 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
     }
 }
 
+// Workgroup size: 16-bit storages use 512 threads, so that in 3-D eight
+// consecutive blocks of the Morton launch order (usually the eight children of
+// one parent) share a CU and its L1; their rows are half as wide and the
+// neighbour reads hit L1 more often.  Wider storages use 256.
+template <int S>
+constexpr int collide_threads() { return sizeof(typename Store<S>::T) <= 2 ? 512 : 256; }
+
 template <int Q, int S>
-__global__ __launch_bounds__(256) void k_collide_stream(const int32_t *__restrict__ list, int n, DevMesh m,
-                                                        const typename Store<S>::T *__restrict__ src,
-                                                        typename Store<S>::T *__restrict__ dst, double omega_d,
-                                                        BCParams bc) {
+__global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
+    const int32_t *__restrict__ list, int n, DevMesh m, const typename Store<S>::T *__restrict__ src,
+    typename Store<S>::T *__restrict__ dst, double omega_d, BCParams bc) {
     using Lt = Lat<Q>;
     using R = typename Store<S>::R;
-    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    constexpr int MB = Lt::MB, BPW = collide_threads<S>() / MB;
     __shared__ BlockStage<Lt, BPW> st;
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int base = wg * BPW;
@@ -1063,7 +1069,8 @@ void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, cons
     if (n <= 0) return;
     const int sp = lp.par[L];
     AMR_DISPATCH(c.q, c.storage,
-                 (k_collide_stream<Qc, Sc><<<grid_blocks(n, c.mb), 256, 0, c.stream>>>(
+                 (k_collide_stream<Qc, Sc><<<(n + collide_threads<Sc>() / c.mb - 1) / (collide_threads<Sc>() / c.mb),
+                                             collide_threads<Sc>(), 0, c.stream>>>(
                      list, n, c.m, TPTR(Sc, c.f[sp]), TPTR(Sc, c.f[1 - sp]), lp.omega[L], bc)));
 }
 
