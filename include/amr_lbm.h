@@ -85,8 +85,14 @@ typedef struct {
 enum amr_tag_kind {
     AMR_TAG_VORTICITY_REL = 0, /* refine leaves whose block vorticity maximum exceeds theta * (max over
                                   all leaves); coarsen refined blocks whose children all fall below */
-    AMR_TAG_DISTANCE = 1       /* refine leaves closer than d_spec / 2^L (root cells) to a solid
+    AMR_TAG_DISTANCE = 1,      /* refine leaves closer than d_spec / 2^L (root cells) to a solid
                                   block or an outflow face; freeze = 1 makes them permanent */
+    AMR_TAG_LADDER = 2         /* Alg. 3: desired level from eps = min(1, log2 |w|), |w| the block
+                                  vorticity maximum in units of domain length 1 along x
+                                  (N_x times the root-lattice value): L_max-1, lowered to
+                                  L_max-1-p for every p = 1 .. L_max-1 with eps < n_start - p n_inc.
+                                  Leaves below it refine; parents whose children all want at most
+                                  the parent's level coarsen */
 };
 
 typedef struct {
@@ -94,6 +100,8 @@ typedef struct {
     double theta;    /* AMR_TAG_VORTICITY_REL */
     double d_spec;   /* AMR_TAG_DISTANCE, root-cell units */
     int32_t freeze;  /* AMR_TAG_DISTANCE */
+    double n_start;  /* AMR_TAG_LADDER */
+    double n_inc;    /* AMR_TAG_LADDER */
 } amr_tag_params;
 
 /* tag values (one int8 per block ID) */

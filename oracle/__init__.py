@@ -45,7 +45,8 @@ class _Config(C.Structure):
 
 
 class _TagParams(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("theta", C.c_double), ("d_spec", C.c_double), ("freeze", C.c_int32)]
+    _fields_ = [("kind", C.c_int32), ("theta", C.c_double), ("d_spec", C.c_double), ("freeze", C.c_int32),
+                ("n_start", C.c_double), ("n_inc", C.c_double)]
 
 
 def lib():
@@ -182,8 +183,8 @@ class Oracle:
         lib().orc_sync(self.h)
 
     def tag(self, kind: int = 0, theta: float = 0.1, d_spec: float = 0.0, freeze: int = 0,
-            tags_in: np.ndarray | None = None) -> np.ndarray:
-        p = _TagParams(kind, theta, d_spec, freeze)
+            tags_in: np.ndarray | None = None, n_start: float = -2.0, n_inc: float = 1.0) -> np.ndarray:
+        p = _TagParams(kind, theta, d_spec, freeze, n_start, n_inc)
         out = np.zeros(self.cap, np.int8)
         tin = None
         if tags_in is not None:

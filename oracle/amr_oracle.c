@@ -740,6 +740,22 @@ static int8_t effective_tag(const orc_t *o, int32_t B, int8_t t)
     return TAG_NONE;
 }
 
+/* Desired level of a block from its maximum vorticity (Sec. "Adaptive Mesh
+ * Refinement" of the solver, Alg. 3): epsilon = min(1, log2 |w|); the level
+ * starts at L_max - 1 and becomes (L_max - 1) - p for every p = 1 .. L_max - 1
+ * (in increasing order) with epsilon < N_start - p N_inc.  Reading: |w| is in
+ * the units of the paper's physical set-ups, domain length 1 along x and
+ * dx = dt = 1/N_x, i.e. N_x times the root-lattice vorticity. */
+static int ladder_level(double w, int lmax, double n_start, double n_inc)
+{
+    double eps = log2(w);
+    if (eps > 1.0) eps = 1.0;
+    int ldes = lmax - 1;
+    for (int p = 1; p <= lmax - 1; p++)
+        if (eps < n_start - p * n_inc) ldes = (lmax - 1) - p;
+    return ldes;
+}
+
 int orc_tag(orc_t *o, const orc_tag_params *prm, const int8_t *tags_in, int8_t *tags_out)
 {
     orc_sync(o);
@@ -747,7 +763,7 @@ int orc_tag(orc_t *o, const orc_tag_params *prm, const int8_t *tags_in, int8_t *
     for (int32_t B = 0; B < o->cap; B++) o->crit[B] = -1.0;
     if (tags_in) {
         memcpy(raw, tags_in, o->cap);
-    } else if (prm->kind == 0) {
+    } else if (prm->kind == 0 || prm->kind == 2) {
         double wmax = 0.0;
         for (int L = 0; L < o->lmax; L++)
             for (int32_t n = 0; n < o->nids[L]; n++) {
@@ -762,10 +778,14 @@ int orc_tag(orc_t *o, const orc_tag_params *prm, const int8_t *tags_in, int8_t *
                 if (m > wmax) wmax = m;
             }
         double thr = prm->theta * wmax;
+        double nx = 4.0 * o->cfg.root[0]; /* domain length along x in root cells */
         int8_t *ldes = (int8_t *)calloc(o->cap, 1);
         for (int32_t B = 0; B < o->cap; B++) {
             if (o->status[B] != ST_UNREFINED) continue;
-            ldes[B] = o->crit[B] > thr ? (int8_t)(o->lmax - 1) : 0;
+            if (prm->kind == 0)
+                ldes[B] = o->crit[B] > thr ? (int8_t)(o->lmax - 1) : 0;
+            else
+                ldes[B] = (int8_t)ladder_level(o->crit[B] * nx, o->lmax, prm->n_start, prm->n_inc);
             if (ldes[B] > o->level[B]) raw[B] = TAG_REFINE;
         }
         for (int32_t P = 0; P < o->cap; P++) {

@@ -41,10 +41,12 @@ typedef struct {
 } orc_config;
 
 typedef struct {
-    int32_t kind;           /* 0 = relative vorticity threshold, 1 = distance to solid / outflow */
+    int32_t kind;           /* 0 = relative vorticity threshold, 1 = distance to solid / outflow,
+                               2 = log2 ladder of the vorticity (Alg. 3) */
     double theta;           /* kind 0: refine where block vorticity > theta * max */
     double d_spec;          /* kind 1: distance in root cells, divided by 2^L on level L */
     int32_t freeze;         /* kind 1: refined blocks become refined-permanent */
+    double n_start, n_inc;  /* kind 2: the ladder's start and increment */
 } orc_tag_params;
 
 typedef struct orc orc_t;

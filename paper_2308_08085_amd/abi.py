@@ -21,7 +21,7 @@ AMR_GET, AMR_SET = 0, 1
 (F_N_OUT, F_CELLS, F_RHO_U, F_F, F_BLOCK_F, F_LEVEL, F_STATUS, F_COORD, F_NBR, F_NBR_CHILD, F_IDSET, F_GAP,
  F_COUNTS, F_MASS_MOM, F_CRIT, F_PARITY, F_KERNEL_STATS) = range(17)
 AMR_CHECK_FINITE, AMR_USE_GRAPH, AMR_PROFILE = 1, 2, 4
-TAG_VORTICITY_REL, TAG_DISTANCE = 0, 1
+TAG_VORTICITY_REL, TAG_DISTANCE, TAG_LADDER = 0, 1, 2
 
 # every symbol the header declares
 EXPORTS = ("amr_query_bytes", "amr_create", "amr_tag", "amr_adapt", "lbm_step", "amr_fields", "amr_destroy",
@@ -45,7 +45,8 @@ class Config(C.Structure):
 
 
 class TagParams(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("theta", C.c_double), ("d_spec", C.c_double), ("freeze", C.c_int32)]
+    _fields_ = [("kind", C.c_int32), ("theta", C.c_double), ("d_spec", C.c_double), ("freeze", C.c_int32),
+                ("n_start", C.c_double), ("n_inc", C.c_double)]
 
 
 class AdaptStats(C.Structure):
@@ -182,8 +183,8 @@ class AmrLbm:
             self._fields(AMR_SET, F_KERNEL_STATS, np.zeros((3, 4), np.float64))
         return {k: tuple(a[i]) for i, k in enumerate(("collide_stream", "interp", "average"))}
 
-    def tag(self, kind=TAG_VORTICITY_REL, theta=0.1, d_spec=0.0, freeze=0, tags_in=None):
-        p = TagParams(kind, theta, d_spec, freeze)
+    def tag(self, kind=TAG_VORTICITY_REL, theta=0.1, d_spec=0.0, freeze=0, tags_in=None, n_start=-2.0, n_inc=1.0):
+        p = TagParams(kind, theta, d_spec, freeze, n_start, n_inc)
         out = np.zeros(self.cap, np.int8)
         tin = None
         if tags_in is not None:

@@ -89,7 +89,14 @@ void launch_batch_items(hipStream_t stream, const SimDesc *sims, int nsims, int 
 // ---- mesh kernels (mesh_kernels.hip) ----
 void launch_init_mesh(const Ctx &c);
 void launch_crit_reset(const Ctx &c);
-void launch_tag_vorticity(const Ctx &c, double theta);
+// block desired levels from the vorticity maxima: relative threshold theta,
+// or (ladder != nullptr) |w| * scale against the ladder thresholds
+// ladder[p] = 2^(n_start - p n_inc), p = 1 .. L_max-1 (+inf when above 2)
+struct LadderParams {
+    double scale;
+    double thr[kMaxLevels];
+};
+void launch_tag_vorticity(const Ctx &c, double theta, const LadderParams *ladder);
 void launch_tag_distance(const Ctx &c, double d_spec, int freeze);
 void launch_effective_tags(const Ctx &c);
 // adaptation after the counts are known on the host

@@ -310,16 +310,31 @@ __global__ void k_crit_reset(double *crit, int cap, DevCounters *ctr) {
 }
 
 // leaves: desired level L_max-1 above theta * max, else 0; refine when above the own level
-__global__ void k_tag_vort_leaf(DevMesh m, const double *crit, const DevCounters *ctr, double theta) {
+// Desired level of each leaf (Sec. "Adaptive Mesh Refinement" of the
+// solver).  Relative threshold: the finest level where the block maximum
+// exceeds theta times the maximum over all leaves, else level 0.  Ladder
+// (Alg. 3): with eps = min(1, log2 |w|), the level L_max-1 is lowered to
+// (L_max-1) - p for every p with eps < n_start - p n_inc; evaluated as
+// |w| < 2^(n_start - p n_inc) against thresholds made on the host (a
+// threshold above 2 always holds, as eps <= 1).
+__global__ void k_tag_vort_leaf(DevMesh m, const double *crit, const DevCounters *ctr, double theta, int ladder,
+                                LadderParams lad) {
     const int B = blockIdx.x * blockDim.x + threadIdx.x;
     if (B >= m.cap) return;
     if (m.status[B] != ST_UNREF) {
         m.tag[B] = 0;
         return;
     }
-    const double wmax = __longlong_as_double((long long)ctr->wmax_bits);
-    const double thr = theta * wmax;
-    const int ldes = crit[B] > thr ? m.lmax - 1 : 0;
+    int ldes;
+    if (ladder) {
+        const double w = crit[B] * lad.scale;
+        ldes = m.lmax - 1;
+        for (int p = 1; p <= m.lmax - 1; p++)
+            if (w < lad.thr[p]) ldes = (m.lmax - 1) - p;
+    } else {
+        const double wmax = __longlong_as_double((long long)ctr->wmax_bits);
+        ldes = crit[B] > theta * wmax ? m.lmax - 1 : 0;
+    }
     m.ldes[B] = (int8_t)ldes;
     m.tag[B] = ldes > m.level[B] ? 1 : 0;
 }
@@ -805,9 +820,11 @@ void connectivity_t(const Ctx &c) {
 }
 
 template <typename Dd>
-void tag_vorticity_t(const Ctx &c, double theta) {
+void tag_vorticity_t(const Ctx &c, double theta, const LadderParams *ladder) {
     const int cap = c.m.cap;
-    k_tag_vort_leaf<<<grid_for(cap), 256, 0, c.stream>>>(c.m, c.crit, c.ctr, theta);
+    LadderParams lad{};
+    if (ladder) lad = *ladder;
+    k_tag_vort_leaf<<<grid_for(cap), 256, 0, c.stream>>>(c.m, c.crit, c.ctr, theta, ladder ? 1 : 0, lad);
     k_tag_vort_parent<Dd><<<grid_for(cap), 256, 0, c.stream>>>(c.m);
 }
 
@@ -824,7 +841,9 @@ void launch_crit_reset(const Ctx &c) {
     k_crit_reset<<<grid_for(c.m.cap), 256, 0, c.stream>>>(c.crit, c.m.cap, c.ctr);
 }
 
-void launch_tag_vorticity(const Ctx &c, double theta) { AMR_DIM_DISPATCH(c.dim, tag_vorticity_t<Dd>(c, theta)); }
+void launch_tag_vorticity(const Ctx &c, double theta, const LadderParams *ladder) {
+    AMR_DIM_DISPATCH(c.dim, tag_vorticity_t<Dd>(c, theta, ladder));
+}
 
 void launch_tag_distance(const Ctx &c, double d_spec, int freeze) {
     DistParams dp;

@@ -453,8 +453,10 @@ amr_status lbm_step(amr_t *h, int32_t n, uint32_t flags) {
 amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int8_t *tags_out) {
     if (!h) return fail(AMR_ERR_ARG, "handle is NULL");
     if (!tags_in && !p) return fail(AMR_ERR_ARG, "criterion parameters are NULL");
-    if (!tags_in && p->kind != AMR_TAG_VORTICITY_REL && p->kind != AMR_TAG_DISTANCE)
+    if (!tags_in && p->kind != AMR_TAG_VORTICITY_REL && p->kind != AMR_TAG_DISTANCE && p->kind != AMR_TAG_LADDER)
         return fail(AMR_ERR_ARG, "unknown criterion kind %d", p->kind);
+    if (!tags_in && p->kind == AMR_TAG_LADDER && !(std::isfinite(p->n_start) && std::isfinite(p->n_inc)))
+        return fail(AMR_ERR_ARG, "n_start and n_inc must be finite");
     Ctx &c = h->c;
     const size_t cap = (size_t)c.m.cap;
     // pre-adaptation synchronisation
@@ -464,11 +466,21 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
     launch_crit_reset(c);
     if (tags_in) {
         HIP_TRY(hipMemcpyAsync(c.m.tag, tags_in, cap, hipMemcpyHostToDevice, c.stream));
-    } else if (p->kind == AMR_TAG_VORTICITY_REL) {
+    } else if (p->kind == AMR_TAG_VORTICITY_REL || p->kind == AMR_TAG_LADDER) {
         const LevelParams lp = level_params(h);
         for (int L = 0; L < h->lmax; L++) launch_velocity(c, c.ids + L * cap, h->nids[L], L, lp);
         for (int L = 0; L < h->lmax; L++) launch_vorticity(c, c.ids + L * cap, h->nids[L], L, lp);
-        launch_tag_vorticity(c, p->theta);
+        if (p->kind == AMR_TAG_LADDER) {
+            LadderParams lad;
+            lad.scale = 4.0 * c.root[0];  // domain length along x in root cells
+            for (int k = 0; k < kMaxLevels; k++) {
+                const double t = p->n_start - k * p->n_inc;
+                lad.thr[k] = t > 1.0 ? INFINITY : std::exp2(t);
+            }
+            launch_tag_vorticity(c, p->theta, &lad);
+        } else {
+            launch_tag_vorticity(c, p->theta, nullptr);
+        }
     } else {
         launch_tag_distance(c, p->d_spec, p->freeze);
     }

@@ -89,6 +89,46 @@ def test_distance_tags():
         assert tags[B] == want, (B, d)
 
 
+def _ladder_by_hand(w, lmax, n_start, n_inc):
+    """Alg. 3 evaluated by hand: the bands of log2 |w| between the thresholds"""
+    eps = min(1.0, np.log2(w)) if w > 0 else -np.inf
+    below = [p for p in range(1, lmax) if eps < n_start - p * n_inc]
+    return (lmax - 1) - max(below) if below else lmax - 1
+
+
+@pytest.mark.parametrize("log2w,want", [(-2.5, 3), (-3.5, 2), (-4.5, 1), (-5.5, 0), (2.0, 3), (-2.99, 3),
+                                         (-3.01, 2), (-10.0, 0)])
+def test_ladder_bands(log2w, want):
+    # N_start = -2, N_inc = 1, L_max = 4: thresholds -3, -4, -5 on epsilon
+    assert _ladder_by_hand(2.0 ** log2w, 4, -2.0, 1.0) == want
+    # the oracle: a uniform shear u_x = a y on a 16^2-cell cavity (N_x = 16 root cells)
+    case = W.cavity(2, 9, 16, 4, 100.0, cap=2000)
+    o = oracle.Oracle(case)
+    m = o.mesh()
+    a = 2.0 ** log2w / 16.0  # root-lattice vorticity; the ladder reads N_x |w|
+    _set_linear_field(o, case, np.array([[0.0, a], [0.0, 0.0]]), m["ids"][0], m)
+    tags = o.tag(kind=2, n_start=-2.0, n_inc=1.0)
+    crit = o.crit()
+    assert np.abs(crit[: case.nroot] * 16.0 - 2.0 ** log2w).max() < 1e-12 * 2.0 ** log2w
+    assert np.all(tags[: case.nroot] == (1 if want > 0 else 0))
+
+
+def test_ladder_coarsens_parents_whose_children_want_less():
+    case = W.cavity(2, 9, 16, 3, 100.0, cap=400)
+    o = oracle.Oracle(case)
+    o.tag(tags_in=np.ones(case.cap, np.int8))
+    o.adapt()
+    m = o.mesh()
+    # desired level 0 everywhere (|w| far below the first threshold): every refined root coarsens
+    _set_linear_field(o, case, np.array([[0.0, 1e-6], [0.0, 0.0]]), m["ids"][1], m)
+    tags = o.tag(kind=2, n_start=-2.0, n_inc=1.0)
+    assert np.all(tags[m["ids"][0]] == -1) and np.all(tags[m["ids"][1]] == 0)
+    # desired level 2 on the children: they refine, the parents stay
+    _set_linear_field(o, case, np.array([[0.0, 0.5], [0.0, 0.0]]), m["ids"][1], m)
+    tags = o.tag(kind=2, n_start=-2.0, n_inc=1.0)
+    assert np.all(tags[m["ids"][1]] == 1) and np.all(tags[m["ids"][0]] == 0)
+
+
 def test_mlups_update_count_hand_counted():
     # 2-D, 4 root blocks, one refined (4 children), one of those refined again
     assert W.mlups_updates([4], 2) == 4 * 16

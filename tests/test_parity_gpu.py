@@ -180,3 +180,24 @@ def test_capacity_error_leaves_mesh_unchanged():
         g.adapt()
     assert e.value.code == abi.AMR_ERR_CAPACITY
     compare_mesh(before, g.mesh())
+
+
+@pytest.mark.parametrize("dim,q", [(2, 9), (3, 19)])
+def test_ladder_criterion_fp64(dim, q):
+    """Alg. 3's log2 ladder (N_start = -2, N_inc = 1) grading a cavity over 3
+    levels: tags equal, tables bit for bit, fields within 1e-12."""
+    case = _cav(dim, q, lmax=3)
+    p = Pair(case)
+    levels_seen = set()
+    for cycle in range(3):
+        p.step(15)
+        tg = p.g.tag(abi.TAG_LADDER, n_start=-2.0, n_inc=1.0)
+        to = p.o.tag(kind=2, n_start=-2.0, n_inc=1.0)
+        assert np.array_equal(tg, to), "ladder tags differ at %s" % np.where(tg != to)[0][:10].tolist()
+        p.adapt()
+        p.check_mesh("ladder cycle %d" % cycle)
+        levels_seen |= {L for L, ids in enumerate(p.g.mesh()["ids"]) if len(ids)}
+    p.step(5)
+    e = p.errors()
+    assert levels_seen == {0, 1, 2}, levels_seen
+    assert e["f"] < 1e-12 and e["u"] < 1e-12 and e["max_drho"] < 1e-12, e
