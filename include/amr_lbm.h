@@ -79,7 +79,16 @@ typedef struct {
                                  highest-priority face it crosses (ties: lower face index) */
     const uint8_t *solid_root; /* host array, one flag per root block in structured order
                                   (x fastest); solid blocks are walls at rest.  Copied; may be NULL */
+    int32_t interp;           /* enum amr_interp: coarse-to-fine interpolation of ghost cells and
+                                 new children */
 } amr_config;
+
+/* Coarse-to-fine interpolation (Sec. "Linear Interpolation" and "Cubic
+ * Interpolation"): the (bi/tri)linear polynomial through the 2^d parent cells
+ * of the child's quadrant, or the tensor-product cubic through all 4^d parent
+ * cells (positions -1/12 + I/6 + 2 I_c/3 in the unit square/cube spanned by
+ * the parent's corner cell centres).  Both act on the rescaled parent cells. */
+enum amr_interp { AMR_INTERP_LINEAR = 0, AMR_INTERP_CUBIC = 1 };
 
 /* Refinement criteria (Sec. "Adaptive Mesh Refinement" of the solver) */
 enum amr_tag_kind {

@@ -40,7 +40,7 @@ class _Config(C.Structure):
         ("dim", C.c_int32), ("q", C.c_int32), ("root", C.c_int32 * 3), ("lmax", C.c_int32),
         ("cap", C.c_int32), ("nu0", C.c_double), ("periodic", C.c_int32 * 3),
         ("face_kind", C.c_int32 * 6), ("face_u", (C.c_double * 3) * 6), ("face_prio", C.c_int32 * 6),
-        ("solid", C.POINTER(C.c_uint8)), ("rescale_mode", C.c_int32),
+        ("solid", C.POINTER(C.c_uint8)), ("rescale_mode", C.c_int32), ("interp", C.c_int32),
     ]
 
 
@@ -63,7 +63,8 @@ def lib():
         L.orc_n_out.argtypes = [P]
         for name in ("orc_set_root_rho_u", "orc_get_block_f", "orc_set_block_f", "orc_step", "orc_sync",
                      "orc_tag", "orc_adapt", "orc_get_crit", "orc_get_out", "orc_mass_mom", "orc_get_mesh",
-                     "orc_lattice", "orc_feq", "orc_collide", "orc_interp_child", "orc_average_parent",
+                     "orc_lattice", "orc_feq", "orc_collide", "orc_interp_child", "orc_interp_child_cubic",
+                     "orc_average_parent",
                      "orc_parity"):
             getattr(L, name).restype = C.c_int32
         _lib = L
@@ -103,10 +104,11 @@ def collide(dim: int, q: int, omega: float, f) -> np.ndarray:
     return out
 
 
-def interp_child(dim: int, q: int, r: float, parent, child: int) -> np.ndarray:
+def interp_child(dim: int, q: int, r: float, parent, child: int, cubic: bool = False) -> np.ndarray:
     parent = np.ascontiguousarray(parent, np.float64)
     out = np.zeros_like(parent)
-    lib().orc_interp_child(dim, q, C.c_double(r), _dp(parent), child, _dp(out))
+    fn = lib().orc_interp_child_cubic if cubic else lib().orc_interp_child
+    fn(dim, q, C.c_double(r), _dp(parent), child, _dp(out))
     return out
 
 
@@ -148,6 +150,7 @@ class Oracle:
             self._solid = np.ascontiguousarray(case.solid, np.uint8)
             cfg.solid = self._solid.ctypes.data_as(C.POINTER(C.c_uint8))
         cfg.rescale_mode = rescale_mode
+        cfg.interp = int(getattr(case, "interp", 0))
         self._h = lib().orc_create(C.byref(cfg))
         if not self._h:
             raise ValueError("oracle rejected the configuration")

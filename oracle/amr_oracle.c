@@ -174,6 +174,45 @@ static double linear_poly(int dim, const double *F /* corners [a + 2b + 4e] */, 
     return a0 + a1 * x + a2 * y + a3 * z + a4 * x * y + a5 * y * z + a6 * x * z + a7 * x * y * z;
 }
 
+/* Coarse-to-fine cubic interpolation (Sec. "Cubic Interpolation").  The
+ * 4^d rescaled parent cells are the sampling points, at (m/3, n/3, e/3) in the
+ * unit square/cube whose corners are the parent's corner cell centres; the
+ * interpolant is the tensor-product polynomial of degree 3 per axis through all
+ * of them (the one the paper's inverted system of monomials x^i y^j z^k
+ * gives), written here as Lagrange interpolation.  Fine cell (I,J,K) of child
+ * (cx,cy,cz) sits at -1/12 + I/6 + 2 cx/3 per axis. */
+static double lagrange3(int m, double x)
+{
+    double v = 1.0;
+    for (int k = 0; k < 4; k++)
+        if (k != m) v *= (x - k / 3.0) / (m / 3.0 - k / 3.0);
+    return v;
+}
+
+static void interp_child_cells_cubic(int dim, int q, const double *g /* rescaled parent, Mb*q */, int child,
+                                     const unsigned char *only, double *out)
+{
+    int mb = dim == 2 ? 16 : 64;
+    int cx = child & 1, cy = (child >> 1) & 1, cz = (child >> 2) & 1;
+    for (int l = 0; l < mb; l++) {
+        if (only && !only[l]) continue;
+        int I = l & 3, J = (l >> 2) & 3, K = l >> 4;
+        double x = -1.0 / 12.0 + I / 6.0 + 2.0 * cx / 3.0;
+        double y = -1.0 / 12.0 + J / 6.0 + 2.0 * cy / 3.0;
+        double z = -1.0 / 12.0 + K / 6.0 + 2.0 * cz / 3.0;
+        for (int p = 0; p < q; p++) {
+            double sum = 0.0;
+            for (int e = 0; e < (dim == 3 ? 4 : 1); e++)
+                for (int n = 0; n < 4; n++)
+                    for (int m = 0; m < 4; m++) {
+                        double wgt = lagrange3(m, x) * lagrange3(n, y) * (dim == 3 ? lagrange3(e, z) : 1.0);
+                        sum += wgt * g[(m + 4 * n + 16 * e) * q + p];
+                    }
+            out[l * q + p] = sum;
+        }
+    }
+}
+
 static void interp_child_cells(int dim, int q, const double *g /* rescaled parent, Mb*q */, int child,
                                const unsigned char *only /* Mb flags or NULL */, double *out)
 {
@@ -196,15 +235,26 @@ static void interp_child_cells(int dim, int q, const double *g /* rescaled paren
     }
 }
 
-int orc_interp_child(int dim, int q, double r, const double *parent, int child, double *out)
+static int interp_child_api(int dim, int q, double r, const double *parent, int child, double *out, int cubic)
 {
     if (!lattice_ok(dim, q)) return -1;
     int mb = dim == 2 ? 16 : 64;
     double *g = (double *)malloc(sizeof(double) * mb * q);
     for (int m = 0; m < mb; m++) rescale_cell(dim, q, r, parent + m * q, g + m * q);
-    interp_child_cells(dim, q, g, child, NULL, out);
+    if (cubic) interp_child_cells_cubic(dim, q, g, child, NULL, out);
+    else interp_child_cells(dim, q, g, child, NULL, out);
     free(g);
     return 0;
+}
+
+int orc_interp_child(int dim, int q, double r, const double *parent, int child, double *out)
+{
+    return interp_child_api(dim, q, r, parent, child, out, 0);
+}
+
+int orc_interp_child_cubic(int dim, int q, double r, const double *parent, int child, double *out)
+{
+    return interp_child_api(dim, q, r, parent, child, out, 1);
 }
 
 /* Fine-to-coarse averaging (Sec. "Averaging").  Parent cell (i,j,k) takes the
@@ -343,6 +393,7 @@ static int is_refined(int8_t s)
 orc_t *orc_create(const orc_config *cfg)
 {
     if (!lattice_ok(cfg->dim, cfg->q) || cfg->lmax < 1 || cfg->lmax > MAXL) return NULL;
+    if (cfg->interp != 0 && cfg->interp != 1) return NULL;
     orc_t *o = (orc_t *)calloc(1, sizeof(orc_t));
     o->cfg = *cfg;
     o->dim = cfg->dim;
@@ -578,7 +629,8 @@ static void interp_parent(orc_t *o, int L, int32_t P, int all_cells)
         }
         double *out = (double *)malloc(sizeof(double) * mb * q);
         memcpy(out, cellf(o, o->par[L + 1], ch, 0), sizeof(double) * mb * q);
-        interp_child_cells(o->dim, q, g, c, all_cells ? NULL : sel, out);
+        if (o->cfg.interp == 1) interp_child_cells_cubic(o->dim, q, g, c, all_cells ? NULL : sel, out);
+        else interp_child_cells(o->dim, q, g, c, all_cells ? NULL : sel, out);
         memcpy(cellf(o, o->par[L + 1], ch, 0), out, sizeof(double) * mb * q);
         free(out);
     }

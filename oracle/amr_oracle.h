@@ -38,6 +38,7 @@ typedef struct {
     int32_t face_prio[6];   /* edge/corner links take the BC of the highest-priority face */
     const uint8_t *solid;   /* per root block (structured order), 1 = solid; may be NULL */
     int32_t rescale_mode;   /* 0 = the paper's rescaling; 1 = deliberately wrong ratio (tests only) */
+    int32_t interp;         /* coarse-to-fine interpolation: 0 = linear, 1 = cubic */
 } orc_config;
 
 typedef struct {
@@ -59,6 +60,8 @@ int orc_feq(int dim, int q, double rho, const double *u, double *out);
 int orc_collide(int dim, int q, double omega, const double *f, double *out);
 /* linear interpolation of all cells of child c of a parent block; parent[Mb*q], out[Mb*q] (cell-major) */
 int orc_interp_child(int dim, int q, double r, const double *parent, int child, double *out);
+/* the same with cubic interpolation (Sec. "Cubic Interpolation") */
+int orc_interp_child_cubic(int dim, int q, double r, const double *parent, int child, double *out);
 /* averaging of all parent cells from their children; children[Nc*Mb*q], out[Mb*q] */
 int orc_average_parent(int dim, int q, double r, const double *children, double *out);
 

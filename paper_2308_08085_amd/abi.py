@@ -40,7 +40,7 @@ class Config(C.Structure):
         ("dim", C.c_int32), ("q", C.c_int32), ("root", C.c_int32 * 3), ("max_levels", C.c_int32),
         ("max_blocks", C.c_int32), ("storage", C.c_int32), ("nu0", C.c_double), ("periodic", C.c_int32 * 3),
         ("face_kind", C.c_int32 * 6), ("face_u", (C.c_double * 3) * 6), ("face_prio", C.c_int32 * 6),
-        ("solid_root", C.POINTER(C.c_uint8)),
+        ("solid_root", C.POINTER(C.c_uint8)), ("interp", C.c_int32),
     ]
 
 
@@ -106,6 +106,7 @@ def make_config(case, storage=None):
     cfg.max_levels, cfg.max_blocks = case.lmax, case.cap
     cfg.storage = STORAGE[storage or case.storage]
     cfg.nu0 = float(case.nu0)
+    cfg.interp = int(getattr(case, "interp", 0))
     for f in range(6):
         cfg.face_kind[f] = int(case.face_kind[f])
         cfg.face_prio[f] = int(case.face_prio[f])

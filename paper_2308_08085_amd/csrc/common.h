@@ -162,6 +162,7 @@ struct DevMesh {
     int32_t lmax;
     int64_t halo_base;  // first halo slot in a distribution buffer (= cap * Q * Mb)
     int32_t nh;         // slots per halo record
+    int32_t interp;     // AMR_INTERP_LINEAR / AMR_INTERP_CUBIC
     int32_t *hid;       // halo record of each block, -1 if it has no N_SKIP link
     int32_t *parent;    // parent block, -1 on the root level
     int8_t *fresh;      // 1 for blocks created by the adaptation in progress

@@ -199,6 +199,7 @@ __device__ inline DevMesh load_mesh(CSimDesc *cs) {
     m.lmax = cs->m.lmax;
     m.halo_base = cs->m.halo_base;
     m.nh = cs->m.nh;
+    m.interp = cs->m.interp;
     m.hid = cs->m.hid;
     m.parent = cs->m.parent;
     m.fresh = cs->m.fresh;
@@ -401,6 +402,55 @@ __device__ inline R lin3(const R *F, R x, R y, R z) {
     return a0 + a1 * x + a2 * y + a3 * z + a4 * x * y + a5 * y * z + a6 * x * z + a7 * x * y * z;
 }
 
+// Weights of the cubic Lagrange polynomials through the nodes u = 0, 1, 2, 3 at u.
+template <typename R>
+__device__ __forceinline__ void lagrange4(R u, R *w) {
+    const R a = u, b = u - R(1), c = u - R(2), d = u - R(3);
+    w[0] = -(b * c * d) / R(6);
+    w[1] = (a * c * d) / R(2);
+    w[2] = -(a * b * d) / R(2);
+    w[3] = (a * b * c) / R(6);
+}
+
+// Interpolated value of fine cell lf of child c from one population of the
+// parent's rescaled cells F[Mb].  Linear: the polynomial through the 2^d
+// parent cells of the quadrant at (-1/4 + I/2, ...).  Cubic (Sec. "Cubic
+// Interpolation"): the tensor product through all 4^d parent cells, nodes at
+// parent cell centres u = 0 .. 3, evaluated at u = 3 (-1/12 + I/6 + 2 c/3)
+// one axis at a time.
+template <typename Lt, typename R>
+__device__ __forceinline__ R interp_value(const R *F, int c, int lf, int cubic) {
+    const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+    const int I = lf & 3, J = (lf >> 2) & 3, K = lf >> 4;
+    if (!cubic) {
+        const R x = R(-0.25) + R(0.5) * R(I), y = R(-0.25) + R(0.5) * R(J), z = R(-0.25) + R(0.5) * R(K);
+        const int m0 = 2 * cx + 4 * (2 * cy) + 16 * (2 * cz);
+        if (Lt::D == 2) return lin2<R>(F[m0], F[m0 + 1], F[m0 + 4], F[m0 + 5], x, y);
+        R G[8];
+#pragma unroll
+        for (int nn = 0; nn < 8; nn++) G[nn] = F[m0 + (nn & 1) + 4 * ((nn >> 1) & 1) + 16 * (nn >> 2)];
+        return lin3<R>(G, x, y, z);
+    }
+    R wx[4], wy[4], wz[4];
+    lagrange4<R>(R(-0.25) + R(0.5) * R(I) + R(2 * cx), wx);
+    lagrange4<R>(R(-0.25) + R(0.5) * R(J) + R(2 * cy), wy);
+    lagrange4<R>(R(-0.25) + R(0.5) * R(K) + R(2 * cz), wz);
+    R v = R(0);
+#pragma unroll
+    for (int e = 0; e < (Lt::D == 3 ? 4 : 1); e++) {
+        R plane = R(0);
+#pragma unroll
+        for (int n = 0; n < 4; n++) {
+            R row = R(0);
+#pragma unroll
+            for (int mm = 0; mm < 4; mm++) row += wx[mm] * F[mm + 4 * n + 16 * e];
+            plane += wy[n] * row;
+        }
+        v += (Lt::D == 3 ? wz[e] : R(1)) * plane;
+    }
+    return v;
+}
+
 template <typename Lt, typename R>
 struct InterpSmem {
     R g[Lt::Q][Lt::MB];
@@ -435,26 +485,15 @@ __device__ __forceinline__ void interp_parent(const DevMesh &m, int P, const typ
         }
     }
     __syncthreads();
+    const int cubic = m.interp;
     for (int e = t; e < NC * MB; e += blockDim.x) {
         const int c = e / MB, lf = e - c * MB;
         if (!((sm.gm[c] >> lf) & 1ull)) continue;
-        const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-        const int I = lf & 3, J = (lf >> 2) & 3, K = lf >> 4;
-        const R x = R(-0.25) + R(0.5) * R(I), y = R(-0.25) + R(0.5) * R(J), z = R(-0.25) + R(0.5) * R(K);
-        const int m0 = 2 * cx + 4 * (2 * cy) + 16 * (2 * cz);
         const int32_t *link = sm.st.link[c];
         const int hc = sm.st.hid[c];
 #pragma unroll
         for (int p = 0; p < Q; p++) {
-            R v;
-            if (Lt::D == 2) {
-                v = lin2<R>(sm.g[p][m0], sm.g[p][m0 + 1], sm.g[p][m0 + 4], sm.g[p][m0 + 5], x, y);
-            } else {
-                R F[8];
-#pragma unroll
-                for (int nn = 0; nn < 8; nn++) F[nn] = sm.g[p][m0 + (nn & 1) + 4 * ((nn >> 1) & 1) + 16 * (nn >> 2)];
-                v = lin3<R>(F, x, y, z);
-            }
+            const R v = interp_value<Lt, R>(sm.g[p], c, lf, cubic);
             store_g<Lt, ST>(dst, entry_slot<Lt>(m, link, first + c, hc, p, lf), p, v);
         }
     }
@@ -570,24 +609,13 @@ __global__ __launch_bounds__(256) void k_refresh_neighbours(const int32_t *__res
             __syncthreads();
             if (t < MB) {
                 const int si = t & 3, sj = (t >> 2) & 3, sk = t >> 4;
-                const int cx = cN & 1, cy = (cN >> 1) & 1, cz = (cN >> 2) & 1;
-                const int m0 = 2 * cx + 4 * (2 * cy) + 16 * (2 * cz);
 #pragma unroll
                 for (int p = 1; p < Q; p++) {
                     const int tx = si + Lt::cx(p), ty = sj + Lt::cy(p), tz = sk + Lt::cz(p);
                     if (region_of<Lt>(tx, ty, tz) != rg) continue;
-                    // cell x of N, and its position in the unit square/cube of N's quadrant
-                    const int I = tx & 3, J = ty & 3, K = tz & 3;
-                    const R x = R(-0.25) + R(0.5) * R(I), y = R(-0.25) + R(0.5) * R(J), z = R(-0.25) + R(0.5) * R(K);
-                    R v;
-                    if (Lt::D == 2) {
-                        v = lin2<R>(s_g[p][m0], s_g[p][m0 + 1], s_g[p][m0 + 4], s_g[p][m0 + 5], x, y);
-                    } else {
-                        R F[8];
-#pragma unroll
-                        for (int nn = 0; nn < 8; nn++) F[nn] = s_g[p][m0 + (nn & 1) + 4 * ((nn >> 1) & 1) + 16 * (nn >> 2)];
-                        v = lin3<R>(F, x, y, z);
-                    }
+                    // cell x of N (quadrant cN of N's parent): its ghost-fill value
+                    const int lx = (tx & 3) + 4 * (ty & 3) + 16 * (tz & 3);
+                    const R v = interp_value<Lt, R>(s_g[p], cN, lx, m.interp);
                     store_g<Lt, ST>(dst, mslot<Lt>(first + c, p, t), p, v);
                 }
             }

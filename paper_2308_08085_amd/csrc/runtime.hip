@@ -63,6 +63,8 @@ amr_status validate(const amr_config *c) {
         return fail(AMR_ERR_ARG, "max_blocks too large for 32-bit cell offsets");
     if (c->storage < AMR_F64 || c->storage > AMR_BF16S) return fail(AMR_ERR_ARG, "unknown storage %d", c->storage);
     if (!(c->nu0 > 0.0)) return fail(AMR_ERR_ARG, "nu0 must be positive");
+    if (c->interp != AMR_INTERP_LINEAR && c->interp != AMR_INTERP_CUBIC)
+        return fail(AMR_ERR_ARG, "unknown interpolation %d", c->interp);
     for (int f = 0; f < 6; f++)
         if (c->face_kind[f] != AMR_FACE_VELOCITY && c->face_kind[f] != AMR_FACE_OUTFLOW)
             return fail(AMR_ERR_ARG, "face_kind[%d] invalid", f);
@@ -295,6 +297,7 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
     c.m.lmax = cfg->max_levels;
     c.m.halo_base = (int64_t)cfg->max_blocks * c.q * c.mb;
     c.m.nh = halo_entries(cfg->q);
+    c.m.interp = cfg->interp;
     c.m.hid = (int32_t *)(a + lay.hid);
     c.m.parent = (int32_t *)(a + lay.parent);
     c.m.fresh = (int8_t *)(a + lay.fresh);

@@ -41,6 +41,7 @@ class Case:
     theta: float = 0.1
     dist_levels: int = 0    # static distance refinement passes at t = 0
     d_spec: float = 0.0     # distance criterion, root cells
+    interp: int = 0         # coarse-to-fine interpolation: 0 linear, 1 cubic
 
     @property
     def mb(self) -> int:

@@ -20,7 +20,13 @@ def mixed_cases():
         W.cavity(3, 19, 32, 2, 400.0, storage="f16s", seed=14),
         W.cavity(2, 9, 16, 4, 100.0, storage="f64", seed=15),
         W.cylinder(3, 27, (32, 16, 16), 4, 8, 3, 100.0, storage="f32s", seed=16, cap=8 * 4 * 4 * 24),
+        _cubic(W.cavity(3, 19, 16, 3, 300.0, storage="f32s", seed=17)),
     ]
+
+
+def _cubic(case):
+    case.interp = 1
+    return case
 
 
 def make(cases, stream=None):

@@ -201,3 +201,95 @@ def test_couette_across_interface_needs_time_unit_rescaling():
     bad = _couette_interface_error(1)
     assert good < 1e-4
     assert bad > 10 * good
+
+
+# ---------------------------------------------------------------------------
+# Cubic interpolation (Sec. "Cubic Interpolation"): positions in parent-cell
+# units, parent cell i at i + 1/2, fine cell I of child c at 2c + (I + 1/2)/2,
+# i.e. the paper's -1/12 + I/6 + 2c/3 in the unit square/cube spanned by the
+# parent's corner cell centres.
+
+def _tensor_cubic(dim, rng, q):
+    a = rng.uniform(-1, 1, size=(4, 4, 4 if dim == 3 else 1, q))
+
+    def f(x, y, z):
+        v = np.zeros(q)
+        for i, j, k in itertools.product(range(4), range(4), range(a.shape[2])):
+            v = v + a[i, j, k] * (x / 4) ** i * (y / 4) ** j * (z / 4) ** k
+        return v + 1.0
+    return f
+
+
+def _parent_and_fine(dim, q, fn, cubic):
+    mb, nc = (16, 4) if dim == 2 else (64, 8)
+    parent = np.zeros((mb, q))
+    for m in range(mb):
+        i, j, k = m & 3, (m >> 2) & 3, m >> 4
+        parent[m] = fn(i + 0.5, j + 0.5, k + 0.5 if dim == 3 else 0.0)
+    err = 0.0
+    for c in range(nc):
+        cx, cy, cz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+        out = oracle.interp_child(dim, q, 1.0, parent, c, cubic=cubic)
+        for l in range(mb):
+            I, J, K = l & 3, (l >> 2) & 3, l >> 4
+            x, y = 2 * cx + (I + 0.5) / 2, 2 * cy + (J + 0.5) / 2
+            z = 2 * cz + (K + 0.5) / 2 if dim == 3 else 0.0
+            err = max(err, np.abs(out[l] - fn(x, y, z)).max())
+    return err
+
+
+@pytest.mark.parametrize("dim,q", LATTICES)
+def test_cubic_interpolation_reproduces_tensor_cubics(dim, q):
+    fn = _tensor_cubic(dim, np.random.default_rng(21), q)
+    assert _parent_and_fine(dim, q, fn, cubic=True) < 1e-12
+    # the linear scheme does not, so the pin tells the two apart
+    assert _parent_and_fine(dim, q, fn, cubic=False) > 1e-3
+
+
+@pytest.mark.parametrize("dim,q", LATTICES)
+def test_cubic_interpolation_reproduces_multilinear(dim, q):
+    fn = _multilinear(dim, np.random.default_rng(22), q)
+    assert _parent_and_fine(dim, q, fn, cubic=True) < 1e-12
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cubic_interpolation_equals_inverted_monomial_system(dim):
+    """the paper's construction: A_UV = x_m^i y_n^j z_l^k at the sampling points,
+    alpha = A^-1 F, F(x) = sum alpha_ijk x^i y^j z^k (solved here with numpy)"""
+    q = 9 if dim == 2 else 19
+    rng = np.random.default_rng(23)
+    mb, nc = (16, 4) if dim == 2 else (64, 8)
+    nz = 4 if dim == 3 else 1
+    F = rng.uniform(0.5, 1.5, size=(mb, q))
+    nodes = [(m / 3.0, n / 3.0, e / 3.0) for e in range(nz) for n in range(4) for m in range(4)]
+    mons = [(i, j, k) for k in range(nz) for j in range(4) for i in range(4)]
+    A = np.array([[x ** i * y ** j * z ** k for (i, j, k) in mons] for (x, y, z) in nodes])
+    alpha = np.linalg.solve(A, F)
+    for c in range(nc):
+        cx, cy, cz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+        out = oracle.interp_child(dim, q, 1.0, F, c, cubic=True)
+        for l in range(mb):
+            I, J, K = l & 3, (l >> 2) & 3, l >> 4
+            x, y, z = -1 / 12 + I / 6 + 2 * cx / 3, -1 / 12 + J / 6 + 2 * cy / 3, -1 / 12 + K / 6 + 2 * cz / 3
+            row = np.array([x ** i * y ** j * (z ** k if dim == 3 else 1.0) for (i, j, k) in mons])
+            assert np.abs(out[l] - row @ alpha).max() < 1e-11
+
+
+@pytest.mark.parametrize("dim,q", [(2, 9), (3, 19)])
+def test_uniform_flow_stays_uniform_with_cubic_interpolation(dim, q):
+    u = np.array([0.03, -0.02, 0.01])[:dim]
+    case = W.cavity(dim, q, 16 if dim == 2 else 8, 3, 50.0, cap=600)
+    case.face_u = tuple(tuple(np.pad(u, (0, 3 - dim))) for _ in range(6))
+    case.interp = 1
+    o = oracle.Oracle(case)
+    ru = np.zeros((case.nroot * case.mb, 4))
+    ru[:, 0] = 1.0
+    ru[:, 1:1 + dim] = u
+    o.set_root_rho_u(ru)
+    _refine_pattern(o, case, [1, 2, case.nroot // 2])
+    m = o.mesh()
+    _refine_pattern(o, case, [m["nbrc"][1, 0] + 1])
+    o.step(3)
+    out = o.output()
+    assert np.abs(out["rho"] - 1.0).max() < 1e-14
+    assert np.abs(out["u"] - u[None, :]).max() < 1e-14

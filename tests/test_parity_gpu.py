@@ -201,3 +201,21 @@ def test_ladder_criterion_fp64(dim, q):
     e = p.errors()
     assert levels_seen == {0, 1, 2}, levels_seen
     assert e["f"] < 1e-12 and e["u"] < 1e-12 and e["max_drho"] < 1e-12, e
+
+
+@pytest.mark.parametrize("dim,q", LATTICES)
+def test_amr_cavity_cubic_interpolation_fp64(dim, q):
+    """cubic coarse-to-fine interpolation (ghost fill, new children, the
+    neighbour refresh) against the oracle's tensor Lagrange form"""
+    case = _cav(dim, q, lmax=3)
+    case.interp = 1
+    p = Pair(case)
+    for cycle in range(3):
+        p.step(20)
+        p.tag_vorticity(0.1)
+        p.adapt()
+        p.check_mesh("cubic cycle %d" % cycle)
+    p.step(10)
+    e = p.errors()
+    assert len(p.g.mesh()["ids"][2]) > 0
+    assert e["f"] < 1e-12 and e["u"] < 1e-12 and e["max_drho"] < 1e-12, e
