@@ -212,6 +212,11 @@ class AmrLbm:
         return {"blk": cells[:, 0].copy(), "cell": cells[:, 1].copy(), "rho": ru[:, 0].copy(),
                 "u": ru[:, 1: 1 + self.dim].copy(), "f": f}
 
+    def rho_u_out(self):
+        """rho, ux, uy, uz of every output cell (no populations: for large meshes)"""
+        n = self.n_out()
+        return self._fields(AMR_GET, F_RHO_U, np.zeros((n, 4), np.float64))
+
     def get_block_f_all(self):
         return self._fields(AMR_GET, F_BLOCK_F, np.zeros((self.cap, self.mb, self.q), np.float64))
 

@@ -1,0 +1,128 @@
+"""The main benchmark set-up at its full size (D3Q27, 256x128x128 root cells,
+near-wall refinement to ~9.7e5 blocks), in the launch configuration the
+benchmark times, checked through properties that hold at any size: a uniform
+flow is a fixed point of the whole step, the tables satisfy the forest
+invariants, and graph replay equals eager launches."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2308_08085_amd import abi, workloads as W
+from meshcheck import block_vectors
+
+pytestmark = pytest.mark.gpu
+
+U = 0.05
+
+
+def full_case(solid=True, storage="f32s"):
+    case = W.config4(cap=W.config4().nroot * 16, storage=storage)
+    if not solid:
+        case.solid = None
+        case.noise = 0.0
+    return case
+
+
+def refine_near_walls(g, case):
+    for _ in range(case.dist_levels):
+        g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=1)
+        g.adapt()
+
+
+def test_uniform_flow_is_a_fixed_point_at_full_size():
+    """no cylinder: inlet and far field at u = (U, 0, 0), outflow at +x; the
+    near-outflow refinement still gives three levels"""
+    case = full_case(solid=False)
+    t0 = time.perf_counter()
+    g = abi.AmrLbm(case)
+    g.set_root_rho_u(case.initial_rho_u())
+    refine_near_walls(g, case)
+    counts = g.counts().tolist()
+    print("full-size uniform flow: blocks per level", counts, flush=True)
+    assert counts[2] > 100000
+    g.step(32, graph=True, check_finite=True)
+    ru = g.rho_u_out()
+    drho = np.abs(ru[:, 0] - 1.0).max()
+    du = max(np.abs(ru[:, 1] - U).max(), np.abs(ru[:, 2:]).max())
+    print("  %d output cells, max |rho - 1| %.2e, max |u - U| %.2e, %.1f s" %
+          (len(ru), drho, du, time.perf_counter() - t0), flush=True)
+    assert drho < 1e-5 and du < 1e-6
+    g.close()
+
+
+def _check_forest_invariants(case, m):
+    cap, lmax = case.cap, case.lmax
+    status, level, X, nbr = m["status"], m["level"], m["X"], m["nbr"]
+    active = status != 8
+    # the ID sets, the gap stack and the solid root blocks (never used) hold
+    # every ID exactly once
+    ids = np.concatenate(m["ids"])
+    solid = np.flatnonzero(case.solid) if case.solid is not None else np.zeros(0, np.int64)
+    every = np.concatenate([ids, m["gap"], solid])
+    assert len(every) == cap and np.array_equal(np.sort(every), np.arange(cap)), "IDs not partitioned"
+    on = np.zeros(cap, bool)
+    on[ids] = True
+    assert np.array_equal(on, active), "ID sets differ from the active blocks"
+    for L in range(lmax):
+        assert np.all(level[m["ids"][L]] == L), "level %d list holds other levels" % L
+    # same-level links: reciprocal and geometric (no periodic axes here)
+    vec = np.array(block_vectors(case.dim))
+    opp = np.array([next(k for k in range(len(vec)) if np.all(vec[k] == -vec[p])) for p in range(len(vec))])
+    W0 = 4 << (lmax - 1)
+    act = np.flatnonzero(active)
+    for p in range(1, len(vec)):
+        B = act
+        N = nbr[B, p]
+        ok = N >= 0
+        B, N = B[ok], N[ok]
+        assert np.all(active[N]), "link to an inactive block"
+        assert np.all(level[N] == level[B]), "link between levels"
+        assert np.all(nbr[N, opp[p]] == B), "link %d not reciprocal" % p
+        width = (W0 >> level[B].astype(np.int64))[:, None]
+        assert np.array_equal(X[N].astype(np.int64), X[B].astype(np.int64) + vec[p][None, :] * width), \
+            "link %d not at the neighbouring position" % p
+    # children tile their parents
+    refined = act[np.isin(status[act], (1, 2, 3))]
+    first = m["nbrc"][refined, 0]
+    assert np.all(first >= 0)
+    for c in range(8):
+        ch = first + c
+        off = np.array([c & 1, (c >> 1) & 1, c >> 2])
+        half = ((W0 >> level[refined].astype(np.int64)) // 2)[:, None]
+        assert np.all(level[ch] == level[refined] + 1)
+        assert np.array_equal(X[ch].astype(np.int64), X[refined].astype(np.int64) + off[None, :] * half)
+
+
+def test_forest_invariants_at_full_size_after_adaptation():
+    case = full_case()
+    g = abi.AmrLbm(case)
+    g.set_root_rho_u(case.initial_rho_u())
+    refine_near_walls(g, case)
+    _check_forest_invariants(case, g.mesh())
+    # the wake needs a few adaptation periods before the criterion changes the mesh
+    for period in range(4):
+        g.step(case.adapt_every, graph=True)
+        g.tag(abi.TAG_VORTICITY_REL, theta=case.theta)
+        st = g.adapt()
+        print("full-size adaptation after period %d:" % (period + 1), st, flush=True)
+        if st["n_refine"] + st["n_coarsen"] > 0:
+            break
+    assert st["n_refine"] + st["n_coarsen"] > 0
+    _check_forest_invariants(case, g.mesh())
+    g.close()
+
+
+def test_graph_replay_equals_eager_at_full_size():
+    case = full_case()
+    runs = []
+    for graph in (True, False):
+        g = abi.AmrLbm(case)
+        g.set_root_rho_u(case.initial_rho_u())
+        refine_near_walls(g, case)
+        g.step(8, graph=graph)
+        runs.append(g.mass_mom())
+        g.close()
+        del g
+    print("mass/momentum graph %s eager %s" % (runs[0], runs[1]), flush=True)
+    assert np.array_equal(runs[0], runs[1])
