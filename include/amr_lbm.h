@@ -208,6 +208,12 @@ amr_status lbm_step(amr_t *h, int32_t n_coarse_steps, uint32_t flags);
  *   AMR_FIELD_CRIT         GET double[max_blocks]: block vorticity maximum of the last
  *                          AMR_TAG_VORTICITY_REL tagging, -1 for non-leaves
  *   AMR_FIELD_PARITY       GET int32[L_max]: buffer (0/1) holding each level's data
+ *   AMR_FIELD_FORCE        GET double[L_max][4]: momentum exchange with the solid blocks (Sec.
+ *                          "Flow Past a Square Cylinder"): per level, the sum over its sweeps of
+ *                          2 f*_q c_q over every post-collision population of a leaf cell whose
+ *                          link ends in a solid block (x, y, z, in that level's lattice units),
+ *                          then the number of sweeps; since the last reset: SET (any buffer),
+ *                          creation, or an amr_adapt that changes the mesh
  *   AMR_FIELD_KERNEL_STATS GET double[3][4]: for the collide-stream, interpolation and averaging
  *                          kernels: launches, summed event time (ms), blocks processed, and the
  *                          distribution bytes those blocks must move, accumulated over lbm_step
@@ -219,7 +225,8 @@ enum amr_field_kind {
     AMR_FIELD_N_OUT = 0, AMR_FIELD_CELLS = 1, AMR_FIELD_RHO_U = 2, AMR_FIELD_F = 3, AMR_FIELD_BLOCK_F = 4,
     AMR_FIELD_LEVEL = 5, AMR_FIELD_STATUS = 6, AMR_FIELD_COORD = 7, AMR_FIELD_NBR = 8,
     AMR_FIELD_NBR_CHILD = 9, AMR_FIELD_IDSET = 10, AMR_FIELD_GAP = 11, AMR_FIELD_COUNTS = 12,
-    AMR_FIELD_MASS_MOM = 13, AMR_FIELD_CRIT = 14, AMR_FIELD_PARITY = 15, AMR_FIELD_KERNEL_STATS = 16
+    AMR_FIELD_MASS_MOM = 13, AMR_FIELD_CRIT = 14, AMR_FIELD_PARITY = 15, AMR_FIELD_KERNEL_STATS = 16,
+    AMR_FIELD_FORCE = 17
 };
 amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf, uint64_t bytes);
 

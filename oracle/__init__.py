@@ -65,7 +65,7 @@ def lib():
                      "orc_tag", "orc_adapt", "orc_get_crit", "orc_get_out", "orc_mass_mom", "orc_get_mesh",
                      "orc_lattice", "orc_feq", "orc_collide", "orc_interp_child", "orc_interp_child_cubic",
                      "orc_average_parent",
-                     "orc_parity"):
+                     "orc_parity", "orc_force"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -194,6 +194,13 @@ class Oracle:
             tin = np.ascontiguousarray(tags_in, np.int8)
             assert tin.shape == (self.cap,)
         lib().orc_tag(self.h, C.byref(p), _ip(tin) if tin is not None else None, _ip(out))
+        return out
+
+    def force(self, reset: bool = False) -> np.ndarray:
+        """[lmax][4]: force on the solid blocks per level (x, y, z) summed over the
+        level's sweeps since the last reset, and the number of sweeps"""
+        out = np.zeros((self.lmax, 4), np.float64)
+        lib().orc_force(self.h, _dp(out), int(reset))
         return out
 
     def adapt(self):

@@ -315,6 +315,8 @@ struct orc {
     int par[MAXL];          /* buffer holding the current data of each level */
     double tau[MAXL];
     double *crit;
+    double *force;          /* cap*3 momentum exchange with solid blocks since the last reset */
+    double sweeps[MAXL];    /* collide-stream sweeps of each level since the last reset */
 };
 
 static const int *bvec(const orc_t *o, int p) { return o->dim == 2 ? VEC2[p] : VEC3[p]; }
@@ -424,6 +426,7 @@ orc_t *orc_create(const orc_config *cfg)
     o->f[0] = (double *)calloc(cap * o->mb * o->q, sizeof(double));
     o->f[1] = (double *)calloc(cap * o->mb * o->q, sizeof(double));
     o->crit = (double *)malloc(cap * sizeof(double));
+    o->force = (double *)calloc((size_t)cap * 3, sizeof(double));
     set_taus(o);
 
     /* root grid: IDs in structured order, all leaves; the gap set holds
@@ -463,7 +466,7 @@ void orc_destroy(orc_t *o)
 {
     if (!o) return;
     free(o->solid); free(o->level); free(o->status); free(o->tag); free(o->X);
-    free(o->nbr); free(o->nbrc); free(o->gap); free(o->f[0]); free(o->f[1]); free(o->crit);
+    free(o->nbr); free(o->nbrc); free(o->gap); free(o->f[0]); free(o->f[1]); free(o->crit); free(o->force);
     for (int L = 0; L < o->lmax; L++) free(o->ids[L]);
     free(o);
 }
@@ -571,13 +574,20 @@ static double boundary_value(const orc_t *o, int32_t code, int p, double fstar, 
  * the opposite slot of the same cell; populations that would arrive from a
  * region covered only by a coarser block are not streamed, and the cell keeps
  * its own post-collision value in that slot (such cells are ghosts). */
+/* The momentum exchange with solid blocks (Sec. "Flow Past a Square
+ * Cylinder"): every post-collision population f*_p of a leaf cell whose link
+ * c_p ends in a solid block is reflected, passing 2 f*_p c_p to the solid.
+ * Summed per block over the sweeps since the last reset, in lattice units of
+ * the block's level. */
 static void collide_stream_level(orc_t *o, int L)
 {
     int src = o->par[L], dst = 1 - o->par[L];
     double omega = 1.0 / o->tau[L];
     int q = o->q, nb = o->nb;
+    o->sweeps[L] += 1.0;
     for (int32_t n = 0; n < o->nids[L]; n++) {
         int32_t B = o->ids[L][n];
+        int leaf = o->status[B] == ST_UNREFINED;
         for (int l = 0; l < o->mb; l++) {
             int ci[3] = {l & 3, (l >> 2) & 3, l >> 4};
             const double *fc = cellf(o, src, B, l);
@@ -597,6 +607,8 @@ static void collide_stream_level(orc_t *o, int L)
                 } else if (code != N_SKIP && code != NONE_ID) {
                     int pb = lattice_opposite(o->dim, p);
                     own[pb] = boundary_value(o, code, p, fs[p], u);
+                    if (code == SOLID_CODE && leaf)
+                        for (int a = 0; a < 3; a++) o->force[(size_t)B * 3 + a] += 2.0 * fs[p] * c[a];
                 }
             }
             for (int p = 0; p < q; p++) {
@@ -877,6 +889,28 @@ int orc_get_crit(orc_t *o, double *out)
  * the top of the gap stack; freed children are pushed back in reverse order of
  * (parent level, parent ID, child index); ID sets drop removed IDs stably and
  * append new children in (parent ID, child index) order. */
+static void reset_force(orc_t *o)
+{
+    memset(o->force, 0, sizeof(double) * 3 * (size_t)o->cap);
+    for (int L = 0; L < MAXL; L++) o->sweeps[L] = 0.0;
+}
+
+/* Per level: force on the solid blocks summed over the active blocks of that
+ * level (x, y, z, in that level's lattice units, summed over its sweeps) and
+ * the number of sweeps since the last reset. */
+int orc_force(orc_t *o, double *out /* [lmax][4] */, int reset)
+{
+    for (int L = 0; L < o->lmax; L++)
+        for (int a = 0; a < 4; a++) out[L * 4 + a] = 0.0;
+    for (int32_t B = 0; B < o->cap; B++) {
+        if (o->status[B] == ST_INACTIVE) continue;
+        for (int a = 0; a < 3; a++) out[o->level[B] * 4 + a] += o->force[(size_t)B * 3 + a];
+    }
+    for (int L = 0; L < o->lmax; L++) out[L * 4 + 3] = o->sweeps[L];
+    if (reset) reset_force(o);
+    return 0;
+}
+
 int orc_adapt(orc_t *o, int32_t *stats)
 {
     int nb = o->nb, nc = o->nc;
@@ -890,6 +924,7 @@ int orc_adapt(orc_t *o, int32_t *stats)
     if (stats) { stats[0] = n_ref; stats[1] = n_coa; stats[2] = 0; stats[3] = 0; }
     if (n_ref == 0 && n_coa == 0) return 0;
     if ((int64_t)nc * n_ref > o->gtop) return -2; /* capacity: nothing changed */
+    reset_force(o); /* blocks are created and removed: the force sums restart */
 
     /* S2: map gaps to refine-marked blocks */
     int32_t *first = (int32_t *)malloc(sizeof(int32_t) * o->cap);

@@ -76,6 +76,10 @@ int orc_step(orc_t *o, int32_t n_coarse_steps);
 int orc_sync(orc_t *o);
 int orc_tag(orc_t *o, const orc_tag_params *p, const int8_t *tags_in, int8_t *tags_out);
 int orc_adapt(orc_t *o, int32_t *stats /* [4]: n_refine, n_coarsen, n_reverted, n_ignored */);
+/* momentum exchange with the solid blocks since the last reset (or mesh
+ * change), per level: out[L*4 + 0..2] force summed over that level's sweeps
+ * in its lattice units, out[L*4 + 3] the number of sweeps */
+int orc_force(orc_t *o, double *out /* [lmax][4] */, int reset);
 /* per-block criterion of the last orc_tag (kind 0), -1 for non-leaves */
 int orc_get_crit(orc_t *o, double *out /* cap */);
 

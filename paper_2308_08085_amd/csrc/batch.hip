@@ -178,6 +178,11 @@ void set_member_parity(amr_batch *b) {
     for (auto *h : b->sims) h->par[0] = b->par0;
 }
 
+void count_member_sweeps(amr_batch *b, int32_t n) {
+    for (auto *h : b->sims)
+        for (int L = 0; L < h->lmax; L++) h->force_sweeps[L] += (double)n * (double)(1 << L);
+}
+
 amr_status run_steps(amr_batch *b, int32_t n, bool use_graph) {
     for (int32_t k = 0; k < n; k++) {
         if (use_graph) {
@@ -206,6 +211,7 @@ amr_status run_steps(amr_batch *b, int32_t n, bool use_graph) {
         b->par0 ^= 1;
     }
     set_member_parity(b);
+    count_member_sweeps(b, n);
     HIP_TRY(hipGetLastError());
     return AMR_OK;
 }

@@ -23,7 +23,7 @@ enum : int8_t {
 __host__ __device__ inline bool is_refined(int s) { return s == ST_REF || s == ST_REF_CHILD || s == ST_REF_PERM; }
 
 // per-block flags kept by the connectivity rebuild
-enum : uint8_t { BF_NSKIP = 1, BF_BOUNDARY = 2, BF_PARENT_MASK = 4 };
+enum : uint8_t { BF_NSKIP = 1, BF_BOUNDARY = 2, BF_PARENT_MASK = 4, BF_SOLID = 8 };
 
 // ---------------------------------------------------------------------------
 // Velocity sets, numbered as in the paper's velocity-set figure.  3-D uses one
@@ -163,6 +163,7 @@ struct DevMesh {
     int64_t halo_base;  // first halo slot in a distribution buffer (= cap * Q * Mb)
     int32_t nh;         // slots per halo record
     int32_t interp;     // AMR_INTERP_LINEAR / AMR_INTERP_CUBIC
+    double *force;      // [cap][3] momentum exchange with solid blocks since the last reset
     int32_t *hid;       // halo record of each block, -1 if it has no N_SKIP link
     int32_t *parent;    // parent block, -1 on the root level
     int8_t *fresh;      // 1 for blocks created by the adaptation in progress

@@ -73,6 +73,9 @@ void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const Lev
 void launch_block_f(const Ctx &c, int set, int b0, int b1, double *stage, const LevelParams &lp);
 void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, void *stage, const LevelParams &lp);
 void launch_mass(const Ctx &c, const LevelParams &lp);
+// momentum exchange with solid blocks: per-level totals out[lmax][3] (device), reset to zero
+void launch_force_sum(const Ctx &c, double *out);
+void launch_force_reset(const Ctx &c);
 
 // ---- batched solver launches: one persistent launch per level over every
 // simulation of a batch (items = simulation << 24 | block, counts on the device)

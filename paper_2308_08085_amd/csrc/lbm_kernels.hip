@@ -200,6 +200,7 @@ __device__ inline DevMesh load_mesh(CSimDesc *cs) {
     m.halo_base = cs->m.halo_base;
     m.nh = cs->m.nh;
     m.interp = cs->m.interp;
+    m.force = cs->m.force;
     m.hid = cs->m.hid;
     m.parent = cs->m.parent;
     m.fresh = cs->m.fresh;
@@ -282,6 +283,11 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
 #pragma unroll
     for (int p = 0; p < Q; p++) g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
 
+    // momentum exchange with solid blocks (Sec. "Flow Past a Square Cylinder"):
+    // a leaf cell's post-collision population f*_q whose link ends in a solid
+    // block is reflected and passes 2 f*_q c_q to it; summed in FP64
+    const bool exchange = (flag & BF_SOLID) && m.status[B] == ST_UNREF;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         if (flag & BF_BOUNDARY) {
@@ -290,6 +296,12 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
                 R val;
                 if (code == kSolid) {
                     val = g[q];
+                    if (exchange) {
+                        const double two_f = 2.0 * (double(g[q]) + Lt::w(q));
+                        fx += two_f * Lt::cx(q);
+                        fy += two_f * Lt::cy(q);
+                        fz += two_f * Lt::cz(q);
+                    }
                 } else {
                     const int face = -3 - code;
                     const R cx = R(Lt::cx(q)), cy = R(Lt::cy(q)), cz = R(Lt::cz(q));
@@ -307,6 +319,19 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
             }
         }
         store_g<Lt, ST>(dst, mslot<Lt>(B, q, l), q, g[q]);
+    }
+    if (exchange) {  // uniform over the block's lanes: sum them, one lane adds to the block's total
+#pragma unroll
+        for (int mask = 1; mask < Lt::MB; mask <<= 1) {
+            fx += __shfl_xor(fx, mask, 64);
+            fy += __shfl_xor(fy, mask, 64);
+            fz += __shfl_xor(fz, mask, 64);
+        }
+        if (l == 0) {
+            m.force[(int64_t)B * 3 + 0] += fx;
+            m.force[(int64_t)B * 3 + 1] += fy;
+            m.force[(int64_t)B * 3 + 2] += fz;
+        }
     }
     if ((flag & BF_NSKIP) && h >= 0) {
 #pragma unroll
@@ -761,6 +786,40 @@ __global__ void k_batch_items(const SimDesc *__restrict__ sims, int nsims, uint3
     const uint32_t tag = (uint32_t)s << kItemSimShift;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s_n; i += gridDim.x * blockDim.x)
         dst[i] = tag | (uint32_t)src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Per-level totals of the momentum exchange over the active blocks (one
+// workgroup per level, fixed summation order): out[L][0..2].
+__global__ __launch_bounds__(256) void k_force_sum(DevMesh m, double *out) {
+    __shared__ double s[3][256];
+    const int L = blockIdx.x, t = threadIdx.x;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int B = t; B < m.cap; B += 256) {
+        if (m.status[B] == ST_INACTIVE || m.level[B] != L) continue;
+        for (int c = 0; c < 3; c++) a[c] += m.force[(int64_t)B * 3 + c];
+    }
+    for (int c = 0; c < 3; c++) s[c][t] = a[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int c = 0; c < 3; c++) s[c][t] += s[c][t + w];
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int c = 0; c < 3; c++) out[L * 3 + c] = s[c][0];
+}
+
+__global__ void k_force_reset(DevMesh m) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (int64_t)m.cap * 3) m.force[e] = 0.0;
+}
+
+void launch_force_sum(const Ctx &c, double *out) { k_force_sum<<<c.m.lmax, 256, 0, c.stream>>>(c.m, out); }
+
+void launch_force_reset(const Ctx &c) {
+    const int64_t n = (int64_t)c.m.cap * 3;
+    k_force_reset<<<(int)((n + 255) / 256), 256, 0, c.stream>>>(c.m);
 }
 
 // ---------------------------------------------------------------------------

@@ -265,7 +265,7 @@ __global__ void k_block_masks(DevMesh m) {
     for (int p = 1; p < Dd::NB; p++) {
         const int32_t n = m.nbr[(int64_t)p * m.cap + B];
         if (n == kNSkip) { fl |= BF_NSKIP; skipset |= 1u << p; }
-        else if (n < 0) fl |= BF_BOUNDARY;
+        else if (n < 0) fl |= n == kSolid ? (BF_BOUNDARY | BF_SOLID) : BF_BOUNDARY;
     }
     uint64_t gm = 0, im = 0;
     if (m.level[B] > 0 && skipset) {

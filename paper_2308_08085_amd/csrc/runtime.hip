@@ -104,6 +104,7 @@ void make_layout(const amr_config *c, Layout *L) {
     L->ids_tmp = take(lmax * cap * 4);
     L->iface = take(lmax * cap * 4);
     L->order = take(lmax * cap * 4);
+    L->force = take(cap * 3 * 8);
     L->gap = take(cap * 4);
     L->first = take(cap * 4);
     L->rlist = take(cap * 4);
@@ -319,6 +320,7 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
     c.ids_tmp = (int32_t *)(a + lay.ids_tmp);
     c.iface = (int32_t *)(a + lay.iface);
     c.order = (int32_t *)(a + lay.order);
+    c.m.force = (double *)(a + lay.force);
     c.gap = (int32_t *)(a + lay.gap);
     c.first = (int32_t *)(a + lay.first);
     c.rlist = (int32_t *)(a + lay.rlist);
@@ -380,6 +382,7 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
         return fail(AMR_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
     }
     launch_fill_rest(c);
+    launch_force_reset(c);
     launch_init_mesh(c);
     s = sync_checked(h);
     if (s == AMR_OK) s = refresh_counts(h);
@@ -437,6 +440,7 @@ amr_status lbm_step(amr_t *h, int32_t n, uint32_t flags) {
         }
     }
     HIP_TRY(hipGetLastError());
+    for (int L = 0; L < h->lmax; L++) h->force_sweeps[L] += (double)n * (double)(1 << L);
     if (h->profiling) {
         amr_status ps = collect_timings(h);
         h->profiling = false;
@@ -509,6 +513,9 @@ amr_status amr_adapt(amr_t *h, amr_adapt_stats *stats) {
     if ((long long)c.nc * n_ref > dc.gtop)
         return fail(AMR_ERR_CAPACITY, "%d refinements need %d free block IDs, %d left", n_ref, c.nc * n_ref, dc.gtop);
     const LevelParams lp = level_params(h);
+    // blocks are created and removed: the momentum-exchange sums restart
+    launch_force_reset(c);
+    for (int L = 0; L < kMaxLevels; L++) h->force_sweeps[L] = 0.0;
     launch_adapt_assign(c, n_ref);
     launch_adapt_build(c, n_ref);
     launch_connectivity(c, c.m.cap);
@@ -545,6 +552,11 @@ amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf
     if (op == AMR_SET && kind == AMR_FIELD_KERNEL_STATS) {
         memset(h->kstats, 0, sizeof(h->kstats));
         return AMR_OK;
+    }
+    if (op == AMR_SET && kind == AMR_FIELD_FORCE) {
+        launch_force_reset(h->c);
+        for (int L = 0; L < kMaxLevels; L++) h->force_sweeps[L] = 0.0;
+        return sync_checked(h);
     }
     if (op == AMR_SET && kind != AMR_FIELD_RHO_U && kind != AMR_FIELD_BLOCK_F)
         return fail(AMR_ERR_ARG, "kind %d cannot be set", kind);
@@ -678,6 +690,20 @@ amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf
     case AMR_FIELD_PARITY: {
         if ((s = need((size_t)h->lmax * 4)) != AMR_OK) return s;
         memcpy(buf, h->par, (size_t)h->lmax * 4);
+        return AMR_OK;
+    }
+    case AMR_FIELD_FORCE: {
+        if ((s = need((size_t)h->lmax * 4 * 8)) != AMR_OK) return s;
+        double *dev = (double *)c.staging;  // >= 1 MB
+        launch_force_sum(c, dev);
+        std::vector<double> tot((size_t)h->lmax * 3);
+        HIP_TRY(hipMemcpyAsync(tot.data(), dev, tot.size() * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        double *out = (double *)buf;
+        for (int L = 0; L < h->lmax; L++) {
+            for (int a = 0; a < 3; a++) out[L * 4 + a] = tot[(size_t)L * 3 + a];
+            out[L * 4 + 3] = h->force_sweeps[L];
+        }
         return AMR_OK;
     }
     default:

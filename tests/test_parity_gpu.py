@@ -219,3 +219,48 @@ def test_amr_cavity_cubic_interpolation_fp64(dim, q):
     e = p.errors()
     assert len(p.g.mesh()["ids"][2]) > 0
     assert e["f"] < 1e-12 and e["u"] < 1e-12 and e["max_drho"] < 1e-12, e
+
+
+def _force_close(fo, fg, what):
+    assert np.array_equal(fo[:, 3], fg[:, 3]), "%s: sweep counts differ %s %s" % (what, fo[:, 3], fg[:, 3])
+    scale = max(np.abs(fo[:, :3]).max(), 1e-300)
+    assert np.abs(fg[:, :3] - fo[:, :3]).max() <= 1e-12 * scale, "%s: oracle %s gpu %s" % (what, fo, fg)
+
+
+@pytest.mark.parametrize("dim,q", [(2, 9), (3, 27)])
+def test_momentum_exchange_force_fp64(dim, q):
+    """force on the cylinder per level (Sec. "Flow Past a Square Cylinder"),
+    across near-wall refinement and a vorticity adaptation"""
+    if dim == 2:
+        case = W.cylinder(2, 9, (64, 32), 8, 16, 3, 100.0, storage="f64", cap=3000, seed=9)
+    else:
+        case = W.cylinder(3, 27, (32, 16, 16), 4, 8, 3, 100.0, storage="f64", cap=12000, seed=10)
+    p = Pair(case)
+    p.step(3)
+    _force_close(p.o.force(), p.g.force(), "before refinement")
+    for _ in range(case.lmax - 1):
+        p.tag_distance(case.d_spec, 1)
+        p.adapt()
+    assert np.all(p.g.force() == 0.0), "adaptation resets the sums"
+    p.step(12)
+    fo, fg = p.o.force(reset=True), p.g.force(reset=True)
+    _force_close(fo, fg, "after near-wall refinement")
+    assert fo[case.lmax - 1, 3] == 12 * 2 ** (case.lmax - 1) and np.abs(fo[case.lmax - 1, :2]).max() > 0
+    p.step(4)
+    p.tag_vorticity(0.1)
+    p.adapt()
+    p.step(5)
+    _force_close(p.o.force(), p.g.force(), "after a vorticity adaptation")
+
+
+def test_force_at_rest_is_the_lattice_pressure_gpu():
+    from test_oracle_force import channel, NX
+    for storage in ("f64", "f32s"):
+        case = channel(0.0, 0.1)
+        g = abi.AmrLbm(case, storage=storage)
+        g.set_root_rho_u(case.initial_rho_u())
+        g.step(5, graph=True)
+        F = g.force()
+        assert F[0, 3] == 5 and abs(F[0, 0]) < 1e-12
+        assert abs(F[0, 1] - (-NX / 3.0) * 5) < (1e-12 if storage == "f64" else 1e-5) * NX, (storage, F)
+        g.close()
