@@ -21,6 +21,7 @@ in the paper; the adaptation time is reported per cycle next to it.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -46,7 +47,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=True):
+def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=True, tag_kind=None):
     import torch
     from paper_2308_08085_amd import abi, workloads as W
 
@@ -58,6 +59,7 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
     period = case.adapt_every
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    refused = [0]
 
     def one_period(profile=False, check=False):
         counts = g.counts().copy()
@@ -66,8 +68,16 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
         ev1.record(g.stream)
         g.synchronize()  # the adaptation clock starts once the advancement has finished
         t0 = time.perf_counter()
-        g.tag(abi.TAG_VORTICITY_REL, theta=theta)
-        g.adapt()
+        if tag_kind == abi.TAG_LADDER:
+            g.tag(abi.TAG_LADDER, n_start=-2.0, n_inc=1.0)
+        else:
+            g.tag(abi.TAG_VORTICITY_REL, theta=theta)
+        try:
+            g.adapt()
+        except abi.AmrError as e:  # atomic refusal: the mesh is unchanged
+            if e.code != abi.AMR_ERR_CAPACITY:
+                raise
+            refused[0] += 1
         t_adapt = time.perf_counter() - t0
         adv_ms = ev0.elapsed_time(ev1)
         return period * W.mlups_updates(counts, case.dim), adv_ms, t_adapt * 1e3, counts
@@ -101,6 +111,7 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
         "wall_s": wall,
         "level_blocks": g.counts().tolist(),
         "kernels": {k: {"launches": int(v[0]), "ms": v[1], "blocks": v[2], "bytes": v[3]} for k, v in ks.items()},
+        "adaptations_refused_for_capacity": refused[0],
     }
     g.close()
     del g
@@ -192,6 +203,71 @@ def run_batch(steps, warmup, theta, trial_steps=2):
         g.close()
     del b, sims
     torch.cuda.empty_cache()
+    return out
+
+
+def run_physics(coarse_steps, storage="f32s"):
+    """Drag, lift and shedding frequency of the D2Q9 square cylinder (1024x256
+    root cells, D = 32, Re 100, 4 levels) from the momentum exchange with the
+    solid blocks, sampled once per adaptation period (32 coarse steps)."""
+    import torch
+    from paper_2308_08085_amd import abi, workloads as W
+
+    case = W.config3(cap=W.config3().nroot * 12)  # near-wall refinement needs ~180k blocks
+    g = abi.AmrLbm(case, storage=storage)
+    g.set_root_rho_u(case.initial_rho_u())
+    for _ in range(case.dist_levels):
+        g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=1)
+        g.adapt()
+    g.force(reset=True)
+    U, D0 = 0.05, 32.0
+    period = case.adapt_every
+    t, cd, cl = [], [], []
+    t0 = time.perf_counter()
+    done = 0
+    while done < coarse_steps:
+        g.step(period, graph=True)
+        done += period
+        F = g.force(reset=True)
+        # mean force per sweep of level L in its own lattice units, to level-0 units:
+        # momentum scales by 2^(-L d), time by 2^(-L), force by 2^(-L (d - 1))
+        sc = [2.0 ** (-L * (case.dim - 1)) / F[L, 3] if F[L, 3] > 0 else 0.0 for L in range(case.lmax)]
+        fx = sum(F[L, 0] * sc[L] for L in range(case.lmax))
+        fy = sum(F[L, 1] * sc[L] for L in range(case.lmax))
+        t.append(done)
+        cd.append(2 * fx / (U * U * D0))
+        cl.append(2 * fy / (U * U * D0))
+        if not np.isfinite(cd[-1]):
+            break
+        g.tag(abi.TAG_VORTICITY_REL, theta=case.theta)
+        try:
+            g.adapt()
+        except abi.AmrError as e:
+            if e.code != abi.AMR_ERR_CAPACITY:
+                raise
+        if len(t) % 100 == 0:
+            log("[physics] coarse step %d: C_D %.4f C_L %.4f (%.0f s)" % (done, cd[-1], cl[-1],
+                                                                         time.perf_counter() - t0))
+    t, cd, cl = np.array(t, float), np.array(cd), np.array(cl)
+    tail = t >= t[-1] * 2.0 / 3.0  # the paper averages over the last 50 of 150 time units
+    # shedding frequency from the upward zero crossings of C_L - mean over the last third
+    x = cl[tail] - cl[tail].mean()
+    up = np.flatnonzero((x[:-1] < 0) & (x[1:] >= 0))
+    st = None
+    if len(up) >= 3:
+        tt = t[tail]
+        # linear interpolation of the crossing times
+        tc = tt[up] + (tt[up + 1] - tt[up]) * (-x[up]) / (x[up + 1] - x[up])
+        f_s = (len(tc) - 1) / (tc[-1] - tc[0])  # per coarse step = per root-lattice time unit
+        st = f_s * D0 / U
+    out = {"workload": "D2Q9 square cylinder, 1024x256 root cells, D = 32, Re 100, 4 levels, %s storage" % storage,
+           "coarse_steps": int(t[-1]), "wall_s": round(time.perf_counter() - t0, 1),
+           "C_D_mean_last_third": round(float(cd[tail].mean()), 4),
+           "C_L_amplitude_last_third": round(float(np.abs(x).max()), 4) if len(x) else None,
+           "St": round(float(st), 4) if st is not None else None,
+           "paper": {"C_D": 1.51, "St": 0.147, "note": "the paper's FP64 runs, its own resolutions"},
+           "level_blocks_end": g.counts().tolist()}
+    g.close()
     return out
 
 
@@ -296,9 +372,21 @@ def main():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-cavity", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true")
+    ap.add_argument("--physics", action="store_true",
+                    help="only the drag / lift / Strouhal run of the D2Q9 square cylinder")
+    ap.add_argument("--physics-steps", type=int, default=153600,
+                    help="coarse steps of the --physics run (150 time units at dt = 1/1024)")
+    ap.add_argument("--physics-storage", default="f32s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device three times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.physics:
+        import torch  # noqa: F401
+        from paper_2308_08085_amd import abi
+        abi.load()
+        print(json.dumps({"physics": run_physics(args.physics_steps, args.physics_storage)}), flush=True)
+        return
     if args.copy_calibration:
         import torch
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -323,6 +411,18 @@ def main():
     r16 = None if args.no_fp16 else run_storage(main_case, "f16s", args.steps, args.warmup, theta)
     c32 = None if args.no_cavity else run_storage(cav, "f32s", args.steps, args.warmup, theta)
     c16 = None if (args.no_cavity or args.no_fp16) else run_storage(cav, "f16s", args.steps, args.warmup, theta)
+    ext = None
+    if not args.no_extensions:
+        # cubic coarse-to-fine interpolation and the log2 criterion ladder on the same set-up
+        cub = dataclasses.replace(main_case, interp=1)
+        rc = run_storage(cub, "f32s", max(2, args.steps // 4), 1, theta)
+        rl = run_storage(main_case, "f32s", max(2, args.steps // 4), 1, theta, tag_kind=abi.TAG_LADDER)
+        ext = {"cubic_interp_f32s": {"mlups": round(rc["mlups"], 1), "kernels": kernel_rates(rc),
+                                     "level_blocks_end": rc["level_blocks"]},
+               "ladder_criterion_f32s": {"n_start": -2.0, "n_inc": 1.0, "mlups": round(rl["mlups"], 1),
+                                         "adapt_ms_per_cycle": round(rl["adapt_ms_per_cycle"], 3),
+                                         "adaptations_refused_for_capacity": rl["adaptations_refused_for_capacity"],
+                                         "level_blocks_end": rl["level_blocks"]}}
     bat = None if args.no_batch else run_batch(max(2, args.steps // 2), 2, theta)
     err = None if args.no_error_leg else error_leg(theta)
     cpu = None if args.no_cpu_baseline else cpu_baseline(theta)
@@ -365,6 +465,8 @@ def main():
         if c16 is not None:
             line["cavity_d3q19"]["mlups_f16s"] = round(c16["mlups"], 1)
             line["cavity_d3q19"]["speedup_f16s_vs_f32s"] = round(c16["mlups"] / c32["mlups"], 3)
+    if ext is not None:
+        line["extensions"] = ext
     if bat is not None:
         line["batched_cfg5"] = bat
     if err is not None:
