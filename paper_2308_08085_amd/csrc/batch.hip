@@ -17,10 +17,11 @@ namespace {
 
 struct Group {
     int q = 0, storage = 0, lmax = 0, cap_max = 0;
+    bool solid = false;        // some member has solid root blocks
     std::vector<int> members;  // indices into amr_batch::sims, in batch order
     SimDesc *desc = nullptr;   // device [members]
-    uint32_t *items = nullptr; // device [2 lmax][stride]
-    int32_t *counts = nullptr; // device [2 lmax]
+    uint32_t *items = nullptr; // device [3 lmax][stride]
+    int32_t *counts = nullptr; // device [3 lmax]
     int64_t stride = 0;        // sum of the members' capacities
     size_t off_desc = 0, off_items = 0, off_counts = 0;
 };
@@ -42,6 +43,7 @@ size_t plan_groups(amr_t *const *sims, int n, std::vector<Group> &groups) {
             g->storage = h->c.storage;
         }
         g->members.push_back(i);
+        g->solid = g->solid || h->c.n_solid > 0;
         g->lmax = std::max(g->lmax, sim_lmax(h));
         g->cap_max = std::max(g->cap_max, h->c.m.cap);
         g->stride += h->c.m.cap;
@@ -54,8 +56,8 @@ size_t plan_groups(amr_t *const *sims, int n, std::vector<Group> &groups) {
     };
     for (auto &g : groups) {
         g.off_desc = take(g.members.size() * sizeof(SimDesc));
-        g.off_items = take((size_t)2 * g.lmax * g.stride * sizeof(uint32_t));
-        g.off_counts = take((size_t)2 * g.lmax * sizeof(int32_t));
+        g.off_items = take((size_t)3 * g.lmax * g.stride * sizeof(uint32_t));
+        g.off_counts = take((size_t)3 * g.lmax * sizeof(int32_t));
     }
     return align256(t);
 }
@@ -112,8 +114,10 @@ SimDesc make_desc(const amr_t *h) {
     d.bc = h->bc;
     d.order = h->c.order;
     d.iface = h->c.iface;
+    d.solid = h->c.solidl;
     d.nids = h->c.ctr->nids;
     d.niface = h->c.ctr->niface;
+    d.nsolid = h->c.ctr->nsolid;
     return d;
 }
 
@@ -127,15 +131,18 @@ void group_level(const amr_batch *b, const Group &g, hipStream_t st, int L, int 
     const bool finer = L + 1 < g.lmax;
     const int64_t s = g.stride;
     if (finer)
-        launch_interp_batch(st, g.q, g.storage, g.desc, g.items + (2 * L + 1) * s, g.counts + 2 * L + 1, L, par[L],
+        launch_interp_batch(st, g.q, g.storage, g.desc, g.items + (3 * L + 1) * s, g.counts + 3 * L + 1, L, par[L],
                             par[L + 1], grid);
-    launch_collide_batch(st, g.q, g.storage, g.desc, g.items + (2 * L) * s, g.counts + 2 * L, L, par[L],
+    launch_collide_batch(st, g.q, g.storage, g.desc, g.items + (3 * L) * s, g.counts + 3 * L, L, par[L],
                          b->tune.threads, grid);
     par[L] ^= 1;
+    if (g.solid)  // momentum exchange with solid blocks, from the buffer just written
+        launch_exchange_batch(st, g.q, g.storage, g.desc, g.items + (3 * L + 2) * s, g.counts + 3 * L + 2, par[L],
+                              std::max(1, b->n_cu));
     if (finer) {
         group_level(b, g, st, L + 1, par);
         group_level(b, g, st, L + 1, par);
-        launch_average_batch(st, g.q, g.storage, g.desc, g.items + (2 * L + 1) * s, g.counts + 2 * L + 1, L, par[L],
+        launch_average_batch(st, g.q, g.storage, g.desc, g.items + (3 * L + 1) * s, g.counts + 3 * L + 1, L, par[L],
                              par[L + 1], grid);
     }
 }

@@ -196,8 +196,10 @@ struct SimDesc {
     BCParams bc;
     const int32_t *order;   // [lmax][cap]
     const int32_t *iface;   // [lmax][cap]
+    const int32_t *solid;   // [lmax][cap] leaf blocks next to a solid block
     const int32_t *nids;    // [kMaxLevels] on the device
     const int32_t *niface;  // [kMaxLevels] on the device
+    const int32_t *nsolid;  // [kMaxLevels] on the device
 };
 
 // batch work item: simulation index in the top 8 bits, block ID below

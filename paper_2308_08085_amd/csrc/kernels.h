@@ -9,6 +9,7 @@ namespace amr {
 struct DevCounters {
     int32_t nids[kMaxLevels];
     int32_t niface[kMaxLevels];
+    int32_t nsolid[kMaxLevels];
     int32_t gtop;
     int32_t n_ref, n_coa, n_rev;
     int32_t nfreed;
@@ -34,6 +35,7 @@ struct Ctx {
     int32_t *ids_tmp;    // [lmax][cap]
     int32_t *iface;      // [lmax][cap]
     int32_t *order;      // [lmax][cap] solver launch order per level (Morton)
+    int32_t *solidl;     // [lmax][cap] leaf blocks next to a solid block, per level
     int32_t *gap;        // [cap]
     int32_t *first;      // [cap]
     int32_t *rank;       // [lmax * cap]
@@ -74,6 +76,9 @@ void launch_block_f(const Ctx &c, int set, int b0, int b1, double *stage, const 
 void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, void *stage, const LevelParams &lp);
 void launch_mass(const Ctx &c, const LevelParams &lp);
 // momentum exchange with solid blocks: per-level totals out[lmax][3] (device), reset to zero
+void launch_exchange(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp);
+void launch_exchange_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
+                           const int32_t *count, int par, int grid);
 void launch_force_sum(const Ctx &c, double *out);
 void launch_force_reset(const Ctx &c);
 
@@ -85,7 +90,8 @@ void launch_interp_batch(hipStream_t stream, int q, int storage, const SimDesc *
                          const int32_t *count, int L, int par0, int par1, int grid);
 void launch_average_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
                           const int32_t *count, int L, int par0, int par1, int grid);
-// items[(2 L + kind) * stride + ...], counts[2 L + kind]: kind 0 launch order, 1 interface parents
+// items[(3 L + kind) * stride + ...], counts[3 L + kind]: kind 0 launch order, 1 interface parents,
+// 2 leaf blocks next to a solid block
 void launch_batch_items(hipStream_t stream, const SimDesc *sims, int nsims, int lmax, int cap_max, uint32_t *items,
                         int64_t stride, int32_t *counts);
 

@@ -283,11 +283,6 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
 #pragma unroll
     for (int p = 0; p < Q; p++) g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
 
-    // momentum exchange with solid blocks (Sec. "Flow Past a Square Cylinder"):
-    // a leaf cell's post-collision population f*_q whose link ends in a solid
-    // block is reflected and passes 2 f*_q c_q to it; summed in FP64
-    const bool exchange = (flag & BF_SOLID) && m.status[B] == ST_UNREF;
-    double fx = 0.0, fy = 0.0, fz = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         if (flag & BF_BOUNDARY) {
@@ -296,12 +291,6 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
                 R val;
                 if (code == kSolid) {
                     val = g[q];
-                    if (exchange) {
-                        const double two_f = 2.0 * (double(g[q]) + Lt::w(q));
-                        fx += two_f * Lt::cx(q);
-                        fy += two_f * Lt::cy(q);
-                        fz += two_f * Lt::cz(q);
-                    }
                 } else {
                     const int face = -3 - code;
                     const R cx = R(Lt::cx(q)), cy = R(Lt::cy(q)), cz = R(Lt::cz(q));
@@ -319,19 +308,6 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
             }
         }
         store_g<Lt, ST>(dst, mslot<Lt>(B, q, l), q, g[q]);
-    }
-    if (exchange) {  // uniform over the block's lanes: sum them, one lane adds to the block's total
-#pragma unroll
-        for (int mask = 1; mask < Lt::MB; mask <<= 1) {
-            fx += __shfl_xor(fx, mask, 64);
-            fy += __shfl_xor(fy, mask, 64);
-            fz += __shfl_xor(fz, mask, 64);
-        }
-        if (l == 0) {
-            m.force[(int64_t)B * 3 + 0] += fx;
-            m.force[(int64_t)B * 3 + 1] += fy;
-            m.force[(int64_t)B * 3 + 2] += fz;
-        }
     }
     if ((flag & BF_NSKIP) && h >= 0) {
 #pragma unroll
@@ -484,7 +460,8 @@ struct InterpSmem {
 };
 
 // Body (whole workgroup): targeted cells of the children of refined parent P.
-template <int Q, int S>
+// CUB: 0 linear, 1 cubic, 2 the mesh's choice at run time.
+template <int Q, int S, int CUB>
 __device__ __forceinline__ void interp_parent(const DevMesh &m, int P, const typename Store<S>::T *src,
                                               typename Store<S>::T *dst, typename Store<S>::R r, int all_cells,
                                               InterpSmem<Lat<Q>, typename Store<S>::R> &sm, int t) {
@@ -510,16 +487,25 @@ __device__ __forceinline__ void interp_parent(const DevMesh &m, int P, const typ
         }
     }
     __syncthreads();
-    const int cubic = m.interp;
+    const int cubic = CUB == 2 ? m.interp : CUB;
     for (int e = t; e < NC * MB; e += blockDim.x) {
         const int c = e / MB, lf = e - c * MB;
         if (!((sm.gm[c] >> lf) & 1ull)) continue;
         const int32_t *link = sm.st.link[c];
         const int hc = sm.st.hid[c];
+        if (cubic) {
+            // 4^d terms per population: not unrolled over the populations
+#pragma unroll 1
+            for (int p = 0; p < Q; p++) {
+                const R v = interp_value<Lt, R>(sm.g[p], c, lf, 1);
+                store_g<Lt, ST>(dst, entry_slot<Lt>(m, link, first + c, hc, p, lf), p, v);
+            }
+        } else {
 #pragma unroll
-        for (int p = 0; p < Q; p++) {
-            const R v = interp_value<Lt, R>(sm.g[p], c, lf, cubic);
-            store_g<Lt, ST>(dst, entry_slot<Lt>(m, link, first + c, hc, p, lf), p, v);
+            for (int p = 0; p < Q; p++) {
+                const R v = interp_value<Lt, R>(sm.g[p], c, lf, 0);
+                store_g<Lt, ST>(dst, entry_slot<Lt>(m, link, first + c, hc, p, lf), p, v);
+            }
         }
     }
 }
@@ -530,7 +516,7 @@ __device__ inline bool interp_target(const DevMesh &m, int P, int nc) {
     return !(first < 0 || first > m.cap - nc || m.level[P] + 1 >= m.lmax);
 }
 
-template <int Q, int S>
+template <int Q, int S, int CUB>
 __global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list, int n, DevMesh m,
                                                 typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
                                                 int all_cells) {
@@ -540,8 +526,8 @@ __global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list
     const int P = list[blockIdx.x];
     if (!interp_target(m, P, Lat<Q>::NC)) return;
     const int L = m.level[P];
-    interp_parent<Q, S>(m, P, lp.par[L] ? f1 : f0, lp.par[L + 1] ? f1 : f0, R(lp.r_cf[L]), all_cells, sm,
-                        threadIdx.x);
+    interp_parent<Q, S, CUB>(m, P, lp.par[L] ? f1 : f0, lp.par[L + 1] ? f1 : f0, R(lp.r_cf[L]), all_cells, sm,
+                             threadIdx.x);
 }
 
 // Batched ghost fill of level L+1 from level L (interface parents of every
@@ -564,8 +550,8 @@ __global__ __launch_bounds__(256) void k_interp_batch(const SimDesc *__restrict_
         CSimDesc *cs = const_view(sims) + sim;
         const DevMesh m = load_mesh(cs);
         if (interp_target(m, P, Lat<Q>::NC))
-            interp_parent<Q, S>(m, P, (const T *)cs->f[par0], (T *)cs->f[par1], R(cs->lp.r_cf[L]), 0, sm,
-                                opaque_tid());
+            interp_parent<Q, S, 2>(m, P, (const T *)cs->f[par0], (T *)cs->f[par1], R(cs->lp.r_cf[L]), 0, sm,
+                                   opaque_tid());
         __syncthreads();
     }
 }
@@ -761,31 +747,116 @@ __global__ __launch_bounds__(512) void k_average_batch(const SimDesc *__restrict
 }
 
 // Work items of a batch for every level: kind 0 = launch order of the level,
-// kind 1 = its interface parents; simulations in batch order.  Grid: x chunks
-// of a list, y = simulation, z = 2 * level + kind.  counts[2 L + kind].
+// kind 1 = its interface parents, kind 2 = its leaf blocks next to a solid
+// block; simulations in batch order.  Grid: x chunks of a list, y =
+// simulation, z = 3 * level + kind.  counts[3 L + kind].
+__device__ inline int item_count(const SimDesc &d, int L, int kind) {
+    if (L >= d.m.lmax) return 0;
+    return kind == 0 ? d.nids[L] : (kind == 1 ? d.niface[L] : d.nsolid[L]);
+}
+
 __global__ void k_batch_items(const SimDesc *__restrict__ sims, int nsims, uint32_t *__restrict__ items,
                               int64_t stride, int32_t *__restrict__ counts) {
-    const int s = blockIdx.y, L = blockIdx.z >> 1, kind = blockIdx.z & 1;
+    const int s = blockIdx.y, L = blockIdx.z / 3, kind = blockIdx.z % 3;
     __shared__ int s_off, s_n;
     if (threadIdx.x == 0) {
         int off = 0;
-        for (int t = 0; t < s; t++) {
-            const SimDesc &o = sims[t];
-            if (L < o.m.lmax) off += kind == 0 ? o.nids[L] : o.niface[L];
-        }
-        const SimDesc &sd = sims[s];
-        const int n = L < sd.m.lmax ? (kind == 0 ? sd.nids[L] : sd.niface[L]) : 0;
+        for (int t = 0; t < s; t++) off += item_count(sims[t], L, kind);
+        const int n = item_count(sims[s], L, kind);
         s_off = off;
         s_n = n;
         if (s == nsims - 1 && blockIdx.x == 0) counts[blockIdx.z] = off + n;
     }
     __syncthreads();
     const SimDesc &sd = sims[s];
-    const int32_t *src = (kind == 0 ? sd.order : sd.iface) + (int64_t)L * sd.m.cap;
+    const int32_t *src = (kind == 0 ? sd.order : (kind == 1 ? sd.iface : sd.solid)) + (int64_t)L * sd.m.cap;
     uint32_t *dst = items + (int64_t)blockIdx.z * stride + s_off;
     const uint32_t tag = (uint32_t)s << kItemSimShift;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s_n; i += gridDim.x * blockDim.x)
         dst[i] = tag | (uint32_t)src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Momentum exchange with solid blocks (Sec. "Flow Past a Square Cylinder"),
+// after a collide-stream sweep: a leaf cell's post-collision population f*_q
+// whose link ends in a solid block was reflected into the cell's own slot
+// (x, q) of the buffer just written; it passes 2 f*_q c_q to the solid.  One
+// block per 64 lanes (2-D: 16), summed over the block, added to its FP64 total
+// (each block's total is written by one lane only).
+template <int Q, int S>
+__device__ __forceinline__ void exchange_block(const DevMesh &m, const BlockStage<Lat<Q>, 256 / Lat<Q>::MB> &st,
+                                               int s, int l, const typename Store<S>::T *f) {
+    using Lt = Lat<Q>;
+    using ST = Store<S>;
+    const int B = st.id[s];
+    if (B < 0) return;
+    const int32_t *link = st.link[s];
+    const int i = l & 3, j = (l >> 2) & 3, k = l >> 4;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll
+    for (int q = 1; q < Q; q++) {
+        if (link[region_of<Lt>(i + Lt::cx(q), j + Lt::cy(q), k + Lt::cz(q))] != kSolid) continue;
+        const double two_f = 2.0 * double(ST::ld(f + mslot<Lt>(B, q, l)) + (ST::shift ? Lt::w(q) : 0.0));
+        fx += two_f * Lt::cx(q);
+        fy += two_f * Lt::cy(q);
+        fz += two_f * Lt::cz(q);
+    }
+#pragma unroll
+    for (int mask = 1; mask < Lt::MB; mask <<= 1) {
+        fx += __shfl_xor(fx, mask, 64);
+        fy += __shfl_xor(fy, mask, 64);
+        fz += __shfl_xor(fz, mask, 64);
+    }
+    if (l == 0) {
+        m.force[(int64_t)B * 3 + 0] += fx;
+        m.force[(int64_t)B * 3 + 1] += fy;
+        m.force[(int64_t)B * 3 + 2] += fz;
+    }
+}
+
+template <int Q, int S>
+__global__ __launch_bounds__(256) void k_exchange(const int32_t *__restrict__ list, int n, DevMesh m,
+                                                  const typename Store<S>::T *__restrict__ f) {
+    using Lt = Lat<Q>;
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
+    const int base = blockIdx.x * BPW;
+    if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
+    __syncthreads();
+    stage_blocks<Lt, BPW>(m, st);
+    exchange_block<Q, S>(m, st, threadIdx.x / MB, threadIdx.x % MB, f);
+}
+
+template <int Q, int S>
+__global__ __launch_bounds__(256) void k_exchange_batch(const SimDesc *__restrict__ sims,
+                                                        const uint32_t *__restrict__ items,
+                                                        const int32_t *__restrict__ count, int par) {
+    using Lt = Lat<Q>;
+    using T = typename Store<S>::T;
+    constexpr int MB = Lt::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lt, BPW> st;
+    const int n = *count;
+    int u0, u1;
+    persistent_range((n + BPW - 1) / BPW, u0, u1);
+    for (int u = u0; u < u1; u++) {
+        if ((int)threadIdx.x < BPW) {
+            const int idx = u * BPW + (int)threadIdx.x;
+            int sim = 0, B = -1;
+            if (idx < n) decode_item(items[idx], sim, B);
+            st.id[threadIdx.x] = B;
+            st.sim[threadIdx.x] = sim;
+        }
+        __syncthreads();
+        stage_blocks_by<Lt, BPW>([&](int e) -> const DevMesh & { return sims[st.sim[e]].m; }, st);
+        const int tid = opaque_tid();
+        const int s = tid / MB;
+        int sim = st.sim[s];
+        if (MB == 64) sim = __builtin_amdgcn_readfirstlane(sim);
+        CSimDesc *cs = const_view(sims) + sim;
+        const DevMesh m = load_mesh(cs);
+        exchange_block<Q, S>(m, st, s, tid % MB, (const T *)cs->f[par]);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1164,9 +1235,27 @@ void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, cons
 void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {
     if (n <= 0) return;
     const int threads = c.dim == 2 ? 64 : 256;
+    if (c.m.interp == AMR_INTERP_CUBIC)
+        AMR_DISPATCH(c.q, c.storage,
+                     (k_interp<Qc, Sc, 1><<<n, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]),
+                                                                        TPTR(Sc, c.f[1]), lp, all_cells)));
+    else
+        AMR_DISPATCH(c.q, c.storage,
+                     (k_interp<Qc, Sc, 0><<<n, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]),
+                                                                        TPTR(Sc, c.f[1]), lp, all_cells)));
+}
+
+void launch_exchange(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp) {
+    if (n <= 0) return;
+    const int bpw = 256 / c.mb;
     AMR_DISPATCH(c.q, c.storage,
-                 (k_interp<Qc, Sc><<<n, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]),
-                                                                 lp, all_cells)));
+                 (k_exchange<Qc, Sc><<<(n + bpw - 1) / bpw, 256, 0, c.stream>>>(list, n, c.m,
+                                                                               TPTR(Sc, c.f[lp.par[L]]))));
+}
+
+void launch_exchange_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
+                           const int32_t *count, int par, int grid) {
+    AMR_DISPATCH(q, storage, (k_exchange_batch<Qc, Sc><<<grid, 256, 0, stream>>>(sims, items, count, par)));
 }
 
 template <int Q, int S>
@@ -1203,7 +1292,7 @@ void launch_batch_items(hipStream_t stream, const SimDesc *sims, int nsims, int 
                         int64_t stride, int32_t *counts) {
     if (nsims <= 0 || lmax <= 0) return;
     const int chunks = std::min(64, (cap_max + 255) / 256);
-    k_batch_items<<<dim3(chunks, nsims, 2 * lmax), 256, 0, stream>>>(sims, nsims, items, stride, counts);
+    k_batch_items<<<dim3(chunks, nsims, 3 * lmax), 256, 0, stream>>>(sims, nsims, items, stride, counts);
 }
 
 void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const LevelParams &lp) {

@@ -744,6 +744,22 @@ void build_order(const Ctx &c) {
     }
 }
 
+// leaf blocks with a link into a solid block, per level in ID order (the
+// blocks whose momentum exchange is summed after each sweep)
+__global__ void k_bins_solid(const DevMesh m, int8_t *bins) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= m.cap) return;
+    bins[B] = (m.status[B] == ST_UNREF && (m.bflag[B] & BF_SOLID)) ? m.level[B] : int8_t(-1);
+}
+
+__global__ void k_solid_lists(const DevMesh m, const int8_t *bins, const int32_t *rank, int32_t *solidl,
+                              DevCounters *ctr) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    if (B < m.cap && bins[B] >= 0) solidl[(int64_t)bins[B] * m.cap + rank[B]] = B;
+    if (B == 0)
+        for (int L = 0; L < kMaxLevels; L++) ctr->nsolid[L] = L < m.lmax ? ctr->totals[L] : 0;
+}
+
 template <typename Dd>
 void masks_and_lists(const Ctx &c) {
     const int cap = c.m.cap;
@@ -757,6 +773,9 @@ void masks_and_lists(const Ctx &c) {
     run_scan(c, c.bins, tot, c.m.lmax);
     k_compact<<<grid_for(tot), 256, 0, c.stream>>>(c.bins, c.rank, c.ids, c.ids_tmp, cap, tot);
     k_copy_lists<<<grid_for(tot), 256, 0, c.stream>>>(c.ids_tmp, c.iface, cap, c.m.lmax, c.ctr, 0);
+    k_bins_solid<<<grid_for(cap), 256, 0, c.stream>>>(c.m, c.bins);
+    run_scan(c, c.bins, cap, c.m.lmax);
+    k_solid_lists<<<grid_for(cap), 256, 0, c.stream>>>(c.m, c.bins, c.rank, c.solidl, c.ctr);
     build_order<Dd>(c);
 }
 

@@ -105,6 +105,7 @@ void make_layout(const amr_config *c, Layout *L) {
     L->iface = take(lmax * cap * 4);
     L->order = take(lmax * cap * 4);
     L->force = take(cap * 3 * 8);
+    L->solidl = take(lmax * cap * 4);
     L->gap = take(cap * 4);
     L->first = take(cap * 4);
     L->rlist = take(cap * 4);
@@ -169,6 +170,9 @@ void collide_stream(amr_handle *h, int L) {
         launch_collide_stream(h->c, h->c.order + (size_t)L * h->c.m.cap, h->nids[L], L, lp, h->bc);
     });
     h->par[L] ^= 1;
+    // momentum exchange with solid blocks, from the buffer just written
+    if (h->nsolid[L] > 0)
+        launch_exchange(h->c, h->c.solidl + (size_t)L * h->c.m.cap, h->nsolid[L], L, level_params(h));
 }
 
 // recursive sub-cycled advancement (Sec. "Grid Advancement")
@@ -220,6 +224,7 @@ amr_status refresh_counts(amr_handle *h) {
     for (int L = 0; L < kMaxLevels; L++) {
         h->nids[L] = L < h->lmax ? dc.nids[L] : 0;
         h->niface[L] = L < h->lmax ? dc.niface[L] : 0;
+        h->nsolid[L] = L < h->lmax ? dc.nsolid[L] : 0;
     }
     h->gtop = dc.gtop;
     return AMR_OK;
@@ -321,6 +326,7 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
     c.iface = (int32_t *)(a + lay.iface);
     c.order = (int32_t *)(a + lay.order);
     c.m.force = (double *)(a + lay.force);
+    c.solidl = (int32_t *)(a + lay.solidl);
     c.gap = (int32_t *)(a + lay.gap);
     c.first = (int32_t *)(a + lay.first);
     c.rlist = (int32_t *)(a + lay.rlist);
@@ -529,11 +535,8 @@ amr_status amr_adapt(amr_t *h, amr_adapt_stats *stats) {
     if (s != AMR_OK) return s;
     s = read_counters(h, &dc);
     if (s != AMR_OK) return s;
-    for (int L = 0; L < kMaxLevels; L++) {
-        h->nids[L] = L < h->lmax ? dc.nids[L] : 0;
-        h->niface[L] = L < h->lmax ? dc.niface[L] : 0;
-    }
-    h->gtop = dc.gtop;
+    s = refresh_counts(h);
+    if (s != AMR_OK) return s;
     drop_graphs(h);
     if (stats) {
         stats->n_refine = n_ref;

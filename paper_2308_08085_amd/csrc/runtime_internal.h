@@ -24,7 +24,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     size_t f[2], nbr, nbrc, X, level, status, tag, ldes, viol, bflag, gmask, imask;
-    size_t ids, ids_tmp, iface, order, force, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
+    size_t ids, ids_tmp, iface, order, force, solidl, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
     size_t crit, part4, solid, solid_list, ctr, staging, staging_bytes, total, hid, U, parent, fresh;
 };
 
@@ -37,7 +37,7 @@ struct amr_handle {
     Ctx c;
     Layout lay;
     int lmax;
-    int nids[kMaxLevels], niface[kMaxLevels];
+    int nids[kMaxLevels], niface[kMaxLevels], nsolid[kMaxLevels];
     int gtop;
     int par[kMaxLevels];
     double force_sweeps[kMaxLevels] = {0};  // collide-stream sweeps per level since the force reset
