@@ -206,69 +206,28 @@ def run_batch(steps, warmup, theta, trial_steps=2):
     return out
 
 
-def run_physics(coarse_steps, storage="f32s"):
-    """Drag, lift and shedding frequency of the D2Q9 square cylinder (1024x256
-    root cells, D = 32, Re 100, 4 levels) from the momentum exchange with the
-    solid blocks, sampled once per adaptation period (32 coarse steps)."""
-    import torch
-    from paper_2308_08085_amd import abi, workloads as W
+# The paper's drag coefficients (linear / cubic interpolation) and Strouhal
+# numbers of the square cylinder at Re 100 with 256 root cells along x, by
+# effective finest resolution 256 * 2^(L_max - 1) (Sec. "Flow Past a Square
+# Cylinder", table of results).
+PAPER_FPSC_256 = {512: (1.581, 1.5010, 0.1469), 1024: (1.584, 1.503, 0.1472),
+                  2048: (1.553, 1.500, 0.1473), 4096: (1.508, 1.498, 0.1472)}
 
-    case = W.config3(cap=W.config3().nroot * 12)  # near-wall refinement needs ~180k blocks
-    g = abi.AmrLbm(case, storage=storage)
-    g.set_root_rho_u(case.initial_rho_u())
-    for _ in range(case.dist_levels):
-        g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=1)
-        g.adapt()
-    g.force(reset=True)
-    U, D0 = 0.05, 32.0
-    period = case.adapt_every
-    t, cd, cl = [], [], []
-    t0 = time.perf_counter()
-    done = 0
-    while done < coarse_steps:
-        g.step(period, graph=True)
-        done += period
-        F = g.force(reset=True)
-        # mean force per sweep of level L in its own lattice units, to level-0 units:
-        # momentum scales by 2^(-L d), time by 2^(-L), force by 2^(-L (d - 1))
-        sc = [2.0 ** (-L * (case.dim - 1)) / F[L, 3] if F[L, 3] > 0 else 0.0 for L in range(case.lmax)]
-        fx = sum(F[L, 0] * sc[L] for L in range(case.lmax))
-        fy = sum(F[L, 1] * sc[L] for L in range(case.lmax))
-        t.append(done)
-        cd.append(2 * fx / (U * U * D0))
-        cl.append(2 * fy / (U * U * D0))
-        if not np.isfinite(cd[-1]):
-            break
-        g.tag(abi.TAG_VORTICITY_REL, theta=case.theta)
-        try:
-            g.adapt()
-        except abi.AmrError as e:
-            if e.code != abi.AMR_ERR_CAPACITY:
-                raise
-        if len(t) % 100 == 0:
-            log("[physics] coarse step %d: C_D %.4f C_L %.4f (%.0f s)" % (done, cd[-1], cl[-1],
-                                                                         time.perf_counter() - t0))
-    t, cd, cl = np.array(t, float), np.array(cd), np.array(cl)
-    tail = t >= t[-1] * 2.0 / 3.0  # the paper averages over the last 50 of 150 time units
-    # shedding frequency from the upward zero crossings of C_L - mean over the last third
-    x = cl[tail] - cl[tail].mean()
-    up = np.flatnonzero((x[:-1] < 0) & (x[1:] >= 0))
-    st = None
-    if len(up) >= 3:
-        tt = t[tail]
-        # linear interpolation of the crossing times
-        tc = tt[up] + (tt[up + 1] - tt[up]) * (-x[up]) / (x[up + 1] - x[up])
-        f_s = (len(tc) - 1) / (tc[-1] - tc[0])  # per coarse step = per root-lattice time unit
-        st = f_s * D0 / U
-    out = {"workload": "D2Q9 square cylinder, 1024x256 root cells, D = 32, Re 100, 4 levels, %s storage" % storage,
-           "coarse_steps": int(t[-1]), "wall_s": round(time.perf_counter() - t0, 1),
-           "C_D_mean_last_third": round(float(cd[tail].mean()), 4),
-           "C_L_amplitude_last_third": round(float(np.abs(x).max()), 4) if len(x) else None,
-           "St": round(float(st), 4) if st is not None else None,
-           "paper": {"C_D": 1.51, "St": 0.147, "note": "the paper's FP64 runs, its own resolutions"},
-           "level_blocks_end": g.counts().tolist()}
-    g.close()
-    return out
+
+def run_physics(n_x, lmax, interp, storage="f64", t_end=150.0, t_avg=140.0):
+    """C_D and St of the paper's square-cylinder run (n_x root cells along x,
+    L_max levels) against the paper's table"""
+    from paper_2308_08085_amd import physics, workloads as W
+
+    case = W.fpsc(n_x, lmax, interp, storage=storage)
+    r = physics.run_fpsc(case, n_x, t_end, t_avg, log=log)
+    n_eff = n_x * 2 ** (lmax - 1)
+    ref = PAPER_FPSC_256.get(n_eff) if n_x == 256 else None
+    return {"workload": case.name, "storage": storage, "n_eff": n_eff, "root_steps": r["root_steps"],
+            "wall_s": r["wall_s"], "samples": r["samples"], "C_D_mean": round(r["C_D_mean"], 4),
+            "C_L_amplitude": round(r["C_L_amplitude"], 4), "St": round(r["St"], 4),
+            "paper": {"C_D": ref[interp], "St": ref[2]} if ref else None,
+            "level_blocks_end": r["level_blocks_end"]}
 
 
 def kernel_rates(res):
@@ -374,10 +333,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-extensions", action="store_true")
     ap.add_argument("--physics", action="store_true",
-                    help="only the drag / lift / Strouhal run of the D2Q9 square cylinder")
-    ap.add_argument("--physics-steps", type=int, default=153600,
-                    help="coarse steps of the --physics run (150 time units at dt = 1/1024)")
-    ap.add_argument("--physics-storage", default="f32s")
+                    help="only the paper's square-cylinder runs: C_D and St against its table")
+    ap.add_argument("--physics-nx", type=int, default=256, help="root cells along x")
+    ap.add_argument("--physics-levels", default="2,3,4,5", help="L_max values, comma-separated")
+    ap.add_argument("--physics-interp", default="linear,cubic")
+    ap.add_argument("--physics-storage", default="f64")
+    ap.add_argument("--physics-t-end", type=float, default=150.0,
+                    help="end time in domain-length units; C_D and St come from its last 10 units")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -385,7 +347,11 @@ def main():
         import torch  # noqa: F401
         from paper_2308_08085_amd import abi
         abi.load()
-        print(json.dumps({"physics": run_physics(args.physics_steps, args.physics_storage)}), flush=True)
+        for lm in [int(x) for x in args.physics_levels.split(",")]:
+            for name in args.physics_interp.split(","):
+                r = run_physics(args.physics_nx, lm, {"linear": 0, "cubic": 1}[name], args.physics_storage,
+                                args.physics_t_end, args.physics_t_end - 10.0)
+                print(json.dumps({"physics": r}), flush=True)
         return
     if args.copy_calibration:
         import torch

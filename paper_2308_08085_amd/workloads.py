@@ -42,6 +42,7 @@ class Case:
     dist_levels: int = 0    # static distance refinement passes at t = 0
     d_spec: float = 0.0     # distance criterion, root cells
     interp: int = 0         # coarse-to-fine interpolation: 0 linear, 1 cubic
+    ladder: tuple | None = None  # (N_start, N_inc) of the log2 criterion ladder, else the relative threshold
 
     @property
     def mb(self) -> int:
@@ -127,6 +128,28 @@ def cylinder(dim: int, q: int, cells: tuple, side: int, x0: int, lmax: int, re: 
                 solid=solid, storage=storage, seed=seed, u_init=(u_in, 0.0, 0.0), steps=steps,
                 adapt_every=adapt_every, theta=theta, dist_levels=lmax - 1,
                 d_spec=0.15 * cells[0])
+
+
+def fpsc(n_x: int = 256, lmax: int = 4, interp: int = 0, storage: str = "f64", seed: int = 2308091,
+         cap: int | None = None) -> Case:
+    """The paper's flow past a square cylinder at Re 100 (Sec. "Flow Past a Square
+    Cylinder", runs F-A to F-C of its parameter table).
+
+    Channel 32 D long and 16 D high (the table's L_fy = 0.5) with n_x root cells
+    along x, so D = n_x / 32; the cylinder's upstream face 10 D from the inlet,
+    centred in y.  Inlet and far field at U = 0.05, outflow at +x, nu from Re 100.
+    Static near-wall refinement with freeze at t = 0, then the log2 ladder with
+    N_start = -3, N_inc = 1 every 32 root steps.  One time unit of the paper
+    (domain length 1) is n_x root steps.
+    """
+    d = n_x // 32
+    case = cylinder(2, 9, (n_x, n_x // 2), d, 10 * d, lmax, 100.0, storage=storage, seed=seed,
+                    name="fpsc_nx%d_l%d_%s" % (n_x, lmax, "cubic" if interp else "linear"),
+                    steps=150 * n_x, adapt_every=32,
+                    cap=cap if cap is not None else (n_x // 4) * (n_x // 8) * 12 * 2 ** lmax)
+    case.interp = interp
+    case.ladder = (-3.0, 1.0)
+    return case
 
 
 # The five set-ups of the benchmark (seed 2308085 + i for set-up i).
