@@ -89,31 +89,44 @@ template <typename Dd> constexpr int kCenterSlot = Dd::D == 2 ? 4 : 13;
 
 // ---------------------------------------------------------------------------
 // Storage formats.  Shifted forms keep g = f - w; arithmetic in R.
+// Storage formats.  stnt is a non-temporal store: a collide-stream sweep's
+// output is read only by the next sweep, after the whole level has streamed
+// through the caches, so keeping it out of L2 leaves room there for the
+// neighbour rows that the gather reads twice.
 template <int S> struct Store;
 template <> struct Store<AMR_F64> {
     using T = double; using R = double; static constexpr bool shift = false;
     __device__ static R ld(const T *p) { return *p; }
     __device__ static void st(T *p, R v) { *p = v; }
+    __device__ static void stnt(T *p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<AMR_F32> {
     using T = float; using R = float; static constexpr bool shift = false;
     __device__ static R ld(const T *p) { return *p; }
     __device__ static void st(T *p, R v) { *p = v; }
+    __device__ static void stnt(T *p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<AMR_F32S> {
     using T = float; using R = float; static constexpr bool shift = true;
     __device__ static R ld(const T *p) { return *p; }
     __device__ static void st(T *p, R v) { *p = v; }
+    __device__ static void stnt(T *p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<AMR_F16S> {
     using T = __half; using R = float; static constexpr bool shift = true;
     __device__ static R ld(const T *p) { return __half2float(*p); }
     __device__ static void st(T *p, R v) { *p = __float2half_rn(v); }
+    __device__ static void stnt(T *p, R v) {
+        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, __float2half_rn(v)), reinterpret_cast<uint16_t *>(p));
+    }
 };
 template <> struct Store<AMR_BF16S> {
     using T = __hip_bfloat16; using R = float; static constexpr bool shift = true;
     __device__ static R ld(const T *p) { return __bfloat162float(*p); }
     __device__ static void st(T *p, R v) { *p = __float2bfloat16(v); }
+    __device__ static void stnt(T *p, R v) {
+        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, __float2bfloat16(v)), reinterpret_cast<uint16_t *>(p));
+    }
 };
 
 inline size_t storage_bytes(int s) { return s == AMR_F64 ? 8 : (s == AMR_F16S || s == AMR_BF16S ? 2 : 4); }

@@ -66,10 +66,13 @@ __device__ __forceinline__ typename ST::R load_g(const typename ST::T *f, int64_
     return ST::shift ? v : v - R(Lt::w(p));
 }
 
-template <typename Lt, typename ST>
+template <typename Lt, typename ST, bool NT = false>
 __device__ __forceinline__ void store_g(typename ST::T *f, int64_t slot, int p, typename ST::R g) {
     using R = typename ST::R;
-    ST::st(f + slot, ST::shift ? g : g + R(Lt::w(p)));
+    if constexpr (NT)
+        ST::stnt(f + slot, ST::shift ? g : g + R(Lt::w(p)));
+    else
+        ST::st(f + slot, ST::shift ? g : g + R(Lt::w(p)));
 }
 
 // gather / scatter all populations of one cell
@@ -240,9 +243,10 @@ __device__ inline void decode_item(uint32_t it, int &sim, int &B) {
 // outgoing populations to its own slots; an outgoing population that would
 // leave the fluid is replaced there by its bounce-back.  A population arriving
 // from a region covered only by a coarser block keeps the cell's own
-// post-collision value (halo record).
+// post-collision value (halo record).  NTS: write with non-temporal stores
+// (for levels whose output is too large to stay cached until the next sweep).
 // Body: the cells of staged block s (this thread: cell l).
-template <int Q, int S, int NBLK>
+template <int Q, int S, int NBLK, bool NTS>
 __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage<Lat<Q>, NBLK> &st, int s, int l,
                                               const typename Store<S>::T *__restrict__ src,
                                               typename Store<S>::T *__restrict__ dst, typename Store<S>::R om,
@@ -272,7 +276,7 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
 #pragma unroll
             for (int p = 0; p < Q; p++) {
                 g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
-                store_g<Lt, ST>(dst, mslot<Lt>(Bu, p, l), p, g[p]);
+                store_g<Lt, ST, NTS>(dst, mslot<Lt>(Bu, p, l), p, g[p]);
             }
             return;
         }
@@ -303,17 +307,17 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
                     }
                 }
                 // the slot now holds population opposite(q) of this cell
-                store_g<Lt, ST>(dst, mslot<Lt>(B, q, l), Lt::opp(q), val);
+                store_g<Lt, ST, NTS>(dst, mslot<Lt>(B, q, l), Lt::opp(q), val);
                 continue;
             }
         }
-        store_g<Lt, ST>(dst, mslot<Lt>(B, q, l), q, g[q]);
+        store_g<Lt, ST, NTS>(dst, mslot<Lt>(B, q, l), q, g[q]);
     }
     if ((flag & BF_NSKIP) && h >= 0) {
 #pragma unroll
         for (int p = 1; p < Q; p++) {
             if (link[region_of<Lt>(i - Lt::cx(p), j - Lt::cy(p), k - Lt::cz(p))] == kNSkip)
-                store_g<Lt, ST>(dst, m.halo_base + (int64_t)h * m.nh + kHalo<Lt>.idx[p][l], p, g[p]);
+                store_g<Lt, ST, NTS>(dst, m.halo_base + (int64_t)h * m.nh + kHalo<Lt>.idx[p][l], p, g[p]);
         }
     }
 }
@@ -325,7 +329,7 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
 template <int S>
 constexpr int collide_threads() { return sizeof(typename Store<S>::T) <= 2 ? 512 : 256; }
 
-template <int Q, int S>
+template <int Q, int S, bool NTS>
 __global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
     const int32_t *__restrict__ list, int n, DevMesh m, const typename Store<S>::T *__restrict__ src,
     typename Store<S>::T *__restrict__ dst, double omega_d, BCParams bc) {
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
     if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
     __syncthreads();
     stage_blocks<Lt, BPW>(m, st);
-    collide_block<Q, S, BPW>(m, st, threadIdx.x / MB, threadIdx.x % MB, src, dst, R(omega_d), bc);
+    collide_block<Q, S, BPW, NTS>(m, st, threadIdx.x / MB, threadIdx.x % MB, src, dst, R(omega_d), bc);
 }
 
 // Batched form: level L of every simulation of a batch in one persistent
@@ -373,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_collide_stream_batch(const SimDesc *__re
         if (MB == 64) sim = __builtin_amdgcn_readfirstlane(sim);  // one block per wave
         CSimDesc *cs = const_view(sims) + sim;
         const DevMesh m = load_mesh(cs);
-        collide_block<Q, S, BPW>(m, st, s, tid % MB, (const T *)cs->f[par], (T *)cs->f[1 - par],
+        collide_block<Q, S, BPW, false>(m, st, s, tid % MB, (const T *)cs->f[par], (T *)cs->f[1 - par],
                                  R(cs->lp.omega[L]), sims[sim].bc);
         __syncthreads();
     }
@@ -1223,13 +1227,28 @@ static inline int grid_blocks(int64_t nblocks, int mb) {
     return (int)((nblocks + bpw - 1) / bpw);
 }
 
+// Output of a level sweep above which its stores bypass the caches: half the
+// 256 MB Infinity Cache.  Smaller levels are still cached when the next sweep
+// (or the interpolation and averaging) reads them.
+constexpr int64_t kStreamingBytes = int64_t(128) << 20;
+
+template <int Q, int S>
+static void collide_stream_nts(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp,
+                               const BCParams &bc) {
+    using T = typename Store<S>::T;
+    const int sp = lp.par[L];
+    const int grid = (n + collide_threads<S>() / c.mb - 1) / (collide_threads<S>() / c.mb);
+    const T *src = (const T *)c.f[sp];
+    T *dst = (T *)c.f[1 - sp];
+    if ((int64_t)n * Q * c.mb * (int64_t)sizeof(T) > kStreamingBytes)
+        k_collide_stream<Q, S, true><<<grid, collide_threads<S>(), 0, c.stream>>>(list, n, c.m, src, dst, lp.omega[L], bc);
+    else
+        k_collide_stream<Q, S, false><<<grid, collide_threads<S>(), 0, c.stream>>>(list, n, c.m, src, dst, lp.omega[L], bc);
+}
+
 void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, const BCParams &bc) {
     if (n <= 0) return;
-    const int sp = lp.par[L];
-    AMR_DISPATCH(c.q, c.storage,
-                 (k_collide_stream<Qc, Sc><<<(n + collide_threads<Sc>() / c.mb - 1) / (collide_threads<Sc>() / c.mb),
-                                             collide_threads<Sc>(), 0, c.stream>>>(
-                     list, n, c.m, TPTR(Sc, c.f[sp]), TPTR(Sc, c.f[1 - sp]), lp.omega[L], bc)));
+    AMR_DISPATCH(c.q, c.storage, (collide_stream_nts<Qc, Sc>(c, list, n, L, lp, bc)));
 }
 
 void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {
