@@ -1,13 +1,15 @@
 """The main benchmark set-up at its full size (D3Q27, 256x128x128 root cells,
-near-wall refinement to ~9.7e5 blocks), in the launch configuration the
-benchmark times, checked through properties that hold at any size: a uniform
-flow is a fixed point of the whole step, the tables satisfy the forest
-invariants, and graph replay equals eager launches."""
+near-wall refinement to ~9.3e5 blocks), in the launch configuration the
+benchmark times: sampled cells against the oracle's single-cell collision,
+and properties that hold at any size (a uniform flow is a fixed point of the
+whole step, the tables satisfy the forest invariants, graph replay equals
+eager launches)."""
 import time
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2308_08085_amd import abi, workloads as W
 from meshcheck import block_vectors
 
@@ -126,3 +128,62 @@ def test_graph_replay_equals_eager_at_full_size():
         del g
     print("mass/momentum graph %s eager %s" % (runs[0], runs[1]), flush=True)
     assert np.array_equal(runs[0], runs[1])
+
+
+@pytest.mark.parametrize("storage", ["f32s", "f16s"])
+def test_sampled_level0_cells_match_the_oracle_at_full_size(storage):
+    """A level-0 leaf whose 26 neighbours are all fluid blocks advances by one
+    collide-stream sweep per coarse step (Secs. "Streaming", "Collision"): the
+    new f_p(x) is population p of the oracle's BGK collision of the pre-step
+    populations at x - c_p.  64 such blocks, every cell and population, after a
+    graph-replayed coarse step of the full set-up."""
+    case = full_case(storage=storage)
+    t0 = time.perf_counter()
+    g = abi.AmrLbm(case)
+    g.set_root_rho_u(case.initial_rho_u())
+    refine_near_walls(g, case)
+    g.step(6, graph=True)  # a developing flow near the cylinder
+    m = g.mesh()
+    nbr = m["nbr"]
+    leaf0 = np.flatnonzero((m["level"] == 0) & (m["status"] == 0))
+    inner = leaf0[np.all(nbr[leaf0] >= 0, axis=1)]
+    assert len(inner) > 1000
+    rng = np.random.default_rng(20230808)
+    # half near the refined region (more structure), half anywhere
+    X = m["X"].astype(np.int64)
+    near = inner[np.argsort(np.abs(X[inner, 0] - 64 * 4))[:2000]]
+    sample = np.unique(np.concatenate([rng.choice(near, 32, replace=False), rng.choice(inner, 32, replace=False)]))
+    vec = np.array(block_vectors(3))
+    c, w, _ = oracle.lattice(3, 27)
+    # the block and its 26 neighbours, as a 12^3-cell region per sample
+    f = g.get_block_f_all()
+    region = np.zeros((len(sample), 12, 12, 12, 27))
+    for s_, B in enumerate(sample):
+        for r in range(27):
+            N = nbr[B, r]
+            ox, oy, oz = 4 * (vec[r] + 1)
+            region[s_, oz:oz + 4, oy:oy + 4, ox:ox + 4] = f[N].reshape(4, 4, 4, 27)
+    del f
+    g.step(1, graph=True)
+    got = g.get_block_f_all()[sample].reshape(len(sample), 4, 4, 4, 27)
+    print("full-size %s: %d sampled level-0 blocks, %.1f s" % (storage, len(sample), time.perf_counter() - t0),
+          flush=True)
+    omega = 1.0 / (3.0 * case.nu0 + 0.5)
+    want = np.zeros_like(got)
+    for s_ in range(len(sample)):
+        post = {}
+        for k in range(4):
+            for j in range(4):
+                for i in range(4):
+                    for p in range(27):
+                        y = (4 + k - c[p, 2], 4 + j - c[p, 1], 4 + i - c[p, 0])
+                        if y not in post:
+                            post[y] = oracle.collide(3, 27, omega, region[(s_,) + y])
+                        want[s_, k, j, i, p] = post[y][p]
+    # storage rounding of the shifted value g = f - w, plus FP32 arithmetic
+    gshift = np.abs(want - w)
+    tol = (2.0 ** -11 * gshift + 2e-7) if storage == "f16s" else (2.0 ** -23 * gshift + 2e-7)
+    err = np.abs(got - want)
+    print("  max |f - oracle| %.3e, max err / tol %.3f" % (err.max(), (err / tol).max()), flush=True)
+    assert np.all(err <= tol)
+    g.close()
