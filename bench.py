@@ -212,19 +212,26 @@ def run_batch(steps, warmup, theta, trial_steps=2):
 # Cylinder", table of results).
 PAPER_FPSC_256 = {512: (1.581, 1.5010, 0.1469), 1024: (1.584, 1.503, 0.1472),
                   2048: (1.553, 1.500, 0.1473), 4096: (1.508, 1.498, 0.1472)}
+# the same table's uniform-grid column: C_D, St
+PAPER_FPSC_UNIFORM = {512: (1.513, 0.1470), 1024: (1.501, 0.1473), 2048: (1.501, 0.1473), 4096: (1.499, 0.1472)}
 
 
-def run_physics(n_x, lmax, interp, storage="f64", t_end=150.0, t_avg=140.0):
+def run_physics(n_x, lmax, interp, storage="f64", t_end=150.0, t_avg=140.0, height=32):
     """C_D and St of the paper's square-cylinder run (n_x root cells along x,
     L_max levels) against the paper's table"""
     from paper_2308_08085_amd import physics, workloads as W
 
-    case = W.fpsc(n_x, lmax, interp, storage=storage)
+    case = W.fpsc(n_x, lmax, interp, storage=storage, height=height)
     r = physics.run_fpsc(case, n_x, t_end, t_avg, log=log)
     n_eff = n_x * 2 ** (lmax - 1)
-    ref = PAPER_FPSC_256.get(n_eff) if n_x == 256 else None
+    if lmax == 1:
+        ref = PAPER_FPSC_UNIFORM.get(n_eff)
+        ref = (ref[0], ref[0], ref[1]) if ref else None
+    else:
+        ref = PAPER_FPSC_256.get(n_eff) if n_x == 256 else None
     return {"workload": case.name, "storage": storage, "n_eff": n_eff, "root_steps": r["root_steps"],
-            "wall_s": r["wall_s"], "samples": r["samples"], "C_D_mean": round(r["C_D_mean"], 4),
+            "wall_s": r["wall_s"], "adapt_s": r["adapt_s"], "samples": r["samples"],
+            "C_D_mean": round(r["C_D_mean"], 4),
             "C_L_amplitude": round(r["C_L_amplitude"], 4), "St": round(r["St"], 4),
             "paper": {"C_D": ref[interp], "St": ref[2]} if ref else None,
             "level_blocks_end": r["level_blocks_end"]}
@@ -338,6 +345,9 @@ def main():
     ap.add_argument("--physics-levels", default="2,3,4,5", help="L_max values, comma-separated")
     ap.add_argument("--physics-interp", default="linear,cubic")
     ap.add_argument("--physics-storage", default="f64")
+    ap.add_argument("--physics-height", type=int, default=32, help="channel height in cylinder diameters")
+    ap.add_argument("--physics-uniform", type=int, default=2048,
+                    help="also run the uniform grid at each effective resolution up to this one (0: none)")
     ap.add_argument("--physics-t-end", type=float, default=150.0,
                     help="end time in domain-length units; C_D and St come from its last 10 units")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -350,7 +360,12 @@ def main():
         for lm in [int(x) for x in args.physics_levels.split(",")]:
             for name in args.physics_interp.split(","):
                 r = run_physics(args.physics_nx, lm, {"linear": 0, "cubic": 1}[name], args.physics_storage,
-                                args.physics_t_end, args.physics_t_end - 10.0)
+                                args.physics_t_end, args.physics_t_end - 10.0, args.physics_height)
+                print(json.dumps({"physics": r}), flush=True)
+            if lm > 1 and args.physics_nx * 2 ** (lm - 1) <= args.physics_uniform:
+                # the uniform grid at the same effective resolution, for C_D, St and the AMR speedup
+                r = run_physics(args.physics_nx * 2 ** (lm - 1), 1, 0, args.physics_storage,
+                                args.physics_t_end, args.physics_t_end - 10.0, args.physics_height)
                 print(json.dumps({"physics": r}), flush=True)
         return
     if args.copy_calibration:

@@ -131,22 +131,23 @@ def cylinder(dim: int, q: int, cells: tuple, side: int, x0: int, lmax: int, re: 
 
 
 def fpsc(n_x: int = 256, lmax: int = 4, interp: int = 0, storage: str = "f64", seed: int = 2308091,
-         cap: int | None = None) -> Case:
+         cap: int | None = None, height: int = 32) -> Case:
     """The paper's flow past a square cylinder at Re 100 (Sec. "Flow Past a Square
     Cylinder", runs F-A to F-C of its parameter table).
 
-    Channel 32 D long and 16 D high (the table's L_fy = 0.5) with n_x root cells
-    along x, so D = n_x / 32; the cylinder's upstream face 10 D from the inlet,
-    centred in y.  Inlet and far field at U = 0.05, outflow at +x, nu from Re 100.
+    Channel 32 D long and `height` D high (the text's square domain by default)
+    with n_x root cells along x, so
+    D = n_x / 32; the cylinder's upstream face 10 D from the inlet, centred in y.  Inlet and far field at U = 0.05, outflow at +x, nu from Re 100.
     Static near-wall refinement with freeze at t = 0, then the log2 ladder with
     N_start = -3, N_inc = 1 every 32 root steps.  One time unit of the paper
     (domain length 1) is n_x root steps.
     """
     d = n_x // 32
-    case = cylinder(2, 9, (n_x, n_x // 2), d, 10 * d, lmax, 100.0, storage=storage, seed=seed,
-                    name="fpsc_nx%d_l%d_%s" % (n_x, lmax, "cubic" if interp else "linear"),
+    ny = height * d
+    case = cylinder(2, 9, (n_x, ny), d, 10 * d, lmax, 100.0, storage=storage, seed=seed,
+                    name="fpsc_nx%d_h%d_l%d_%s" % (n_x, height, lmax, "cubic" if interp else "linear"),
                     steps=150 * n_x, adapt_every=32,
-                    cap=cap if cap is not None else (n_x // 4) * (n_x // 8) * 12 * 2 ** lmax)
+                    cap=cap if cap is not None else (n_x // 4) * (ny // 4) * (12 * 2 ** lmax if lmax > 1 else 1))
     case.interp = interp
     case.ladder = (-3.0, 1.0)
     return case
