@@ -214,6 +214,11 @@ amr_status lbm_step(amr_t *h, int32_t n_coarse_steps, uint32_t flags);
  *                          link ends in a solid block (x, y, z, in that level's lattice units),
  *                          then the number of sweeps; since the last reset: SET (any buffer),
  *                          creation, or an amr_adapt that changes the mesh
+ *   AMR_FIELD_FORCE_ON     GET/SET int32[1]: 1 (the default) = accumulate the momentum
+ *                          exchange in every lbm_step and batch step, 0 = skip its launches
+ *                          and sweep counts (for runs that sample the force only part of the
+ *                          time); SET accepts 0 or 1 (else AMR_ERR_ARG) and re-captures the
+ *                          step graphs when the value changes
  *   AMR_FIELD_KERNEL_STATS GET double[3][4]: for the collide-stream, interpolation and averaging
  *                          kernels: launches, summed event time (ms), blocks processed, and the
  *                          distribution bytes those blocks must move, accumulated over lbm_step
@@ -226,7 +231,7 @@ enum amr_field_kind {
     AMR_FIELD_LEVEL = 5, AMR_FIELD_STATUS = 6, AMR_FIELD_COORD = 7, AMR_FIELD_NBR = 8,
     AMR_FIELD_NBR_CHILD = 9, AMR_FIELD_IDSET = 10, AMR_FIELD_GAP = 11, AMR_FIELD_COUNTS = 12,
     AMR_FIELD_MASS_MOM = 13, AMR_FIELD_CRIT = 14, AMR_FIELD_PARITY = 15, AMR_FIELD_KERNEL_STATS = 16,
-    AMR_FIELD_FORCE = 17
+    AMR_FIELD_FORCE = 17, AMR_FIELD_FORCE_ON = 18
 };
 amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf, uint64_t bytes);
 

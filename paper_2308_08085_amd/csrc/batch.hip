@@ -19,6 +19,7 @@ struct Group {
     int q = 0, storage = 0, lmax = 0, cap_max = 0;
     bool solid = false;        // some member has solid root blocks
     std::vector<int> members;  // indices into amr_batch::sims, in batch order
+    std::vector<bool> force_on;  // each member's momentum-exchange switch in the uploaded descriptors
     SimDesc *desc = nullptr;   // device [members]
     uint32_t *items = nullptr; // device [3 lmax][stride]
     int32_t *counts = nullptr; // device [3 lmax]
@@ -118,6 +119,7 @@ SimDesc make_desc(const amr_t *h) {
     d.nids = h->c.ctr->nids;
     d.niface = h->c.ctr->niface;
     d.nsolid = h->c.ctr->nsolid;
+    d.force_on = h->force_on ? 1 : 0;
     return d;
 }
 
@@ -187,7 +189,28 @@ void set_member_parity(amr_batch *b) {
 
 void count_member_sweeps(amr_batch *b, int32_t n) {
     for (auto *h : b->sims)
-        for (int L = 0; L < h->lmax; L++) h->force_sweeps[L] += (double)n * (double)(1 << L);
+        if (h->force_on)
+            for (int L = 0; L < h->lmax; L++) h->force_sweeps[L] += (double)n * (double)(1 << L);
+}
+
+// A member whose momentum-exchange switch changed since its descriptor was
+// uploaded gets its group's descriptors again (the work lists are built from
+// them on the device, so captured steps stay valid).
+amr_status refresh_descs(amr_batch *b) {
+    for (auto &g : b->groups) {
+        bool stale = false;
+        for (size_t k = 0; k < g.members.size(); k++)
+            stale = stale || g.force_on[k] != b->sims[g.members[k]]->force_on;
+        if (!stale) continue;
+        std::vector<SimDesc> host;
+        for (size_t k = 0; k < g.members.size(); k++) {
+            host.push_back(make_desc(b->sims[g.members[k]]));
+            g.force_on[k] = b->sims[g.members[k]]->force_on;
+        }
+        HIP_TRY(hipMemcpyAsync(g.desc, host.data(), host.size() * sizeof(SimDesc), hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+    }
+    return AMR_OK;
 }
 
 amr_status run_steps(amr_batch *b, int32_t n, bool use_graph) {
@@ -278,6 +301,7 @@ amr_status amr_batch_create(amr_t *const *sims, int32_t n, void *dev_arena, uint
         g.counts = (int32_t *)(a + g.off_counts);
         std::vector<SimDesc> host;
         for (int i : g.members) host.push_back(make_desc(sims[i]));
+        for (int i : g.members) g.force_on.push_back(sims[i]->force_on);
         if (e == hipSuccess)
             e = hipMemcpyAsync(g.desc, host.data(), host.size() * sizeof(SimDesc), hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -306,7 +330,9 @@ amr_status amr_batch_step(amr_batch_t *b, int32_t n, uint32_t flags) {
     if (flags & AMR_PROFILE) return fail(AMR_ERR_ARG, "AMR_PROFILE is not available for batches");
     for (auto *h : b->sims)
         if (h->par[0] != b->par0) return fail(AMR_ERR_STATE, "a member was stepped outside the batch");
-    amr_status s = run_steps(b, n, (flags & AMR_USE_GRAPH) != 0);
+    amr_status s = refresh_descs(b);
+    if (s != AMR_OK) return s;
+    s = run_steps(b, n, (flags & AMR_USE_GRAPH) != 0);
     if (s != AMR_OK) return s;
     if (flags & AMR_CHECK_FINITE) {
         int bad = -1;

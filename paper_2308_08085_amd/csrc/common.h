@@ -213,6 +213,7 @@ struct SimDesc {
     const int32_t *nids;    // [kMaxLevels] on the device
     const int32_t *niface;  // [kMaxLevels] on the device
     const int32_t *nsolid;  // [kMaxLevels] on the device
+    int32_t force_on;       // accumulate the momentum exchange (else no solid items)
 };
 
 // batch work item: simulation index in the top 8 bits, block ID below

@@ -756,7 +756,7 @@ __global__ __launch_bounds__(512) void k_average_batch(const SimDesc *__restrict
 // simulation, z = 3 * level + kind.  counts[3 L + kind].
 __device__ inline int item_count(const SimDesc &d, int L, int kind) {
     if (L >= d.m.lmax) return 0;
-    return kind == 0 ? d.nids[L] : (kind == 1 ? d.niface[L] : d.nsolid[L]);
+    return kind == 0 ? d.nids[L] : (kind == 1 ? d.niface[L] : (d.force_on ? d.nsolid[L] : 0));
 }
 
 __global__ void k_batch_items(const SimDesc *__restrict__ sims, int nsims, uint32_t *__restrict__ items,

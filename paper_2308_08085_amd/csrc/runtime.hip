@@ -171,7 +171,7 @@ void collide_stream(amr_handle *h, int L) {
     });
     h->par[L] ^= 1;
     // momentum exchange with solid blocks, from the buffer just written
-    if (h->nsolid[L] > 0)
+    if (h->force_on && h->nsolid[L] > 0)
         launch_exchange(h->c, h->c.solidl + (size_t)L * h->c.m.cap, h->nsolid[L], L, level_params(h));
 }
 
@@ -446,7 +446,8 @@ amr_status lbm_step(amr_t *h, int32_t n, uint32_t flags) {
         }
     }
     HIP_TRY(hipGetLastError());
-    for (int L = 0; L < h->lmax; L++) h->force_sweeps[L] += (double)n * (double)(1 << L);
+    if (h->force_on)
+        for (int L = 0; L < h->lmax; L++) h->force_sweeps[L] += (double)n * (double)(1 << L);
     if (h->profiling) {
         amr_status ps = collect_timings(h);
         h->profiling = false;
@@ -554,6 +555,20 @@ amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf
     if (op != AMR_GET && op != AMR_SET) return fail(AMR_ERR_ARG, "op must be AMR_GET or AMR_SET");
     if (op == AMR_SET && kind == AMR_FIELD_KERNEL_STATS) {
         memset(h->kstats, 0, sizeof(h->kstats));
+        return AMR_OK;
+    }
+    if (kind == AMR_FIELD_FORCE_ON) {
+        if (!buf || bytes < 4) return fail(AMR_ERR_ARG, "AMR_FIELD_FORCE_ON needs an int32 buffer");
+        int32_t *v = (int32_t *)buf;
+        if (op == AMR_GET) {
+            *v = h->force_on ? 1 : 0;
+            return AMR_OK;
+        }
+        if (*v != 0 && *v != 1) return fail(AMR_ERR_ARG, "AMR_FIELD_FORCE_ON takes 0 or 1, not %d", *v);
+        if ((*v == 1) != h->force_on) {
+            h->force_on = *v == 1;
+            drop_graphs(h);  // captured steps hold the exchange launches, or not
+        }
         return AMR_OK;
     }
     if (op == AMR_SET && kind == AMR_FIELD_FORCE) {

@@ -66,6 +66,7 @@ def run_fpsc(case, n_x: int, t_end: float = 150.0, t_avg: float = 140.0, sample:
     U, D = float(case.face_u[0][0]), float(n_x // 32)
     g = abi.AmrLbm(case)
     try:
+        g.force_accumulation(False)  # until the sampling window opens
         g.set_root_rho_u(case.initial_rho_u())
         for _ in range(case.dist_levels):
             g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=1)
@@ -84,6 +85,7 @@ def run_fpsc(case, n_x: int, t_end: float = 150.0, t_avg: float = 140.0, sample:
                 g.step(period, graph=True)
                 done += period
                 if done == n_avg:
+                    g.force_accumulation(True)
                     g.force(reset=True)
             else:
                 for _ in range(period // sample):

@@ -264,3 +264,52 @@ def test_force_at_rest_is_the_lattice_pressure_gpu():
         assert F[0, 3] == 5 and abs(F[0, 0]) < 1e-12
         assert abs(F[0, 1] - (-NX / 3.0) * 5) < (1e-12 if storage == "f64" else 1e-5) * NX, (storage, F)
         g.close()
+
+
+def test_force_switch_skips_the_exchange_and_keeps_the_fields():
+    """AMR_FIELD_FORCE_ON = 0 skips the momentum-exchange pass (no sums, no
+    sweep counts) and changes nothing else; switched back on, the sums match a
+    run that never switched; batches follow each member's switch"""
+    import torch
+    case = W.cylinder(3, 27, (32, 16, 16), 4, 8, 3, 100.0, storage="f64", cap=12000, seed=10)
+    shared = torch.cuda.Stream()
+    runs = []
+    for _ in range(3):
+        g = abi.AmrLbm(case, stream=shared)
+        g.set_root_rho_u(case.initial_rho_u())
+        for _ in range(case.lmax - 1):
+            g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=1)
+            g.adapt()
+        runs.append(g)
+    a, b, c = runs
+    assert b.force_accumulation() and not b.force_accumulation(False)
+    a.step(4, graph=True)
+    b.step(4, graph=True)
+    assert np.all(b.force() == 0.0), b.force()
+    assert np.array_equal(a.get_block_f_all(), b.get_block_f_all())
+    assert b.force_accumulation(True)
+    a.force(reset=True)
+    a.step(3, graph=True)
+    b.step(3, graph=True)
+    Fa, Fb = a.force(), b.force()
+    assert Fa[:, 3].sum() > 0 and np.array_equal(Fa, Fb)
+    with pytest.raises(abi.AmrError) as e:
+        b._fields(abi.AMR_SET, abi.F_FORCE_ON, np.array([2], np.int32))
+    assert e.value.code == abi.AMR_ERR_ARG
+    # batch of b and c: c off, b on
+    c.step(7, graph=True)
+    for g in (b, c):
+        g.force(reset=True)
+    c.force_accumulation(False)
+    bt = abi.AmrBatch([b, c])
+    bt.step(2, graph=True)
+    assert np.all(c.force() == 0.0)
+    a.force(reset=True)
+    a.step(2, graph=True)
+    assert np.array_equal(b.force(), a.force())
+    c.force_accumulation(True)
+    bt.step(2, graph=True)  # the same captured steps, descriptors refreshed
+    a.force(reset=True)
+    a.step(2, graph=True)
+    assert np.array_equal(c.force(), a.force())  # c accumulated only these two steps
+    bt.close()
