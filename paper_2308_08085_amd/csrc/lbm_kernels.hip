@@ -685,8 +685,17 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, const ty
     const int child = first + c;
     const uint64_t im = all_cells ? ~0ull : m.imask[child];
     if (im == 0) return;  // the whole child (a wave in 3-D, a 16-lane group in 2-D)
+    // the 2^d lanes of one parent cell (cell-index bits 0, 2 and, in 3-D, 4)
+    // are exactly the partners of the sums below: a group whose parent cell
+    // is not written loads nothing
+    const int lead = lf & ~(Lt::D == 3 ? 0x15 : 0x5);
     R g[Q];
-    gather_cell<Lt, ST>(m, st.link[c], child, st.hid[c], lf, src, g);
+    if ((im >> lead) & 1ull) {
+        gather_cell<Lt, ST>(m, st.link[c], child, st.hid[c], lf, src, g);
+    } else {
+#pragma unroll
+        for (int p = 0; p < Q; p++) g[p] = R(0);
+    }
     R drho, ux, uy, uz;
     moments_g<Lt, R>(g, drho, ux, uy, uz);
     const R uu = ux * ux + uy * uy + uz * uz;
@@ -700,7 +709,7 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, const ty
         g[p] = v;
     }
     const int i = lf & 3, j = (lf >> 2) & 3, k = lf >> 4;
-    if (((i | j | k) & 1) || !((im >> lf) & 1ull)) return;
+    if (lf != lead || !((im >> lf) & 1ull)) return;
     const int l = ((c & 1) * 2 + (i >> 1)) + 4 * (((c >> 1) & 1) * 2 + (j >> 1)) + 16 * ((c >> 2) * 2 + (k >> 1));
     const int32_t *plink = st.link[NC];
     const int ph = st.hid[NC];
