@@ -1053,7 +1053,11 @@ __global__ __launch_bounds__(256) void k_vorticity(const int32_t *__restrict__ l
     for (int off = MB / 2; off > 0; off >>= 1) w = fmax(w, __shfl_xor(w, off, 64));
     if (leaf && l == 0) {
         crit[B] = w;
-        atomicMax(wmax_bits, (unsigned long long)__double_as_longlong(w));
+        // the running maximum rarely grows: compare first, so that most blocks
+        // skip the atomic on the one shared address
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(w);
+        if (bits > __hip_atomic_load(wmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(wmax_bits, bits);
     }
 }
 
