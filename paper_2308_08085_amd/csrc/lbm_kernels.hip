@@ -1194,11 +1194,12 @@ __global__ __launch_bounds__(256) void k_mass_blocks(DevMesh m, typename Store<S
         for (int a = 0; a < 4; a++) part4[(int64_t)Braw * 4 + a] = v[a];
 }
 
-__global__ __launch_bounds__(256) void k_mass_final(const double *part4, int cap, double *out) {
-    __shared__ double s[4][256];
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int B = threadIdx.x; B < cap; B += 256)
-        for (int a = 0; a < 4; a++) v[a] += part4[(int64_t)B * 4 + a];
+// Fixed-order sums of the per-block partials: each workgroup reduces one chunk
+// of kMassChunk blocks and leaves the result in the chunk's first entry (which
+// no other workgroup reads); one workgroup then reduces the chunk results.
+constexpr int kMassChunk = 4096;
+
+__device__ inline void tree_sum4(double (*s)[256], double *v) {
     for (int a = 0; a < 4; a++) s[a][threadIdx.x] = v[a];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -1206,6 +1207,26 @@ __global__ __launch_bounds__(256) void k_mass_final(const double *part4, int cap
             for (int a = 0; a < 4; a++) s[a][threadIdx.x] += s[a][threadIdx.x + w];
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void k_mass_chunks(double *part4, int cap) {
+    __shared__ double s[4][256];
+    const int64_t b0 = (int64_t)blockIdx.x * kMassChunk;
+    const int64_t b1 = b0 + kMassChunk < cap ? b0 + kMassChunk : cap;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t B = b0 + threadIdx.x; B < b1; B += 256)
+        for (int a = 0; a < 4; a++) v[a] += part4[B * 4 + a];
+    tree_sum4(s, v);  // ends with a barrier: every read of the chunk is done
+    if (threadIdx.x < 4) part4[b0 * 4 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_mass_final(const double *part4, int cap, double *out) {
+    __shared__ double s[4][256];
+    const int nchunk = (cap + kMassChunk - 1) / kMassChunk;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < nchunk; c += 256)
+        for (int a = 0; a < 4; a++) v[a] += part4[(int64_t)c * kMassChunk * 4 + a];
+    tree_sum4(s, v);
     if (threadIdx.x < 4) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
@@ -1392,6 +1413,7 @@ void launch_mass(const Ctx &c, const LevelParams &lp) {
     AMR_DISPATCH(c.q, c.storage,
                  (k_mass_blocks<Qc, Sc><<<grid_blocks(c.m.cap, c.mb), 256, 0, c.stream>>>(
                      c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]), lp, c.part4)));
+    k_mass_chunks<<<(c.m.cap + kMassChunk - 1) / kMassChunk, 256, 0, c.stream>>>(c.part4, c.m.cap);
     k_mass_final<<<1, 256, 0, c.stream>>>(c.part4, c.m.cap, c.ctr->mass);
 }
 
