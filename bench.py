@@ -60,6 +60,7 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     refused = [0]
+    steps_ms = {k: 0.0 for k in abi.ADAPT_STEPS}  # device time per adaptation step, summed
 
     def one_period(profile=False, check=False):
         counts = g.counts().copy()
@@ -73,7 +74,9 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
         else:
             g.tag(abi.TAG_VORTICITY_REL, theta=theta)
         try:
-            g.adapt()
+            st = g.adapt()
+            for k, v in st["step_ms"].items():
+                steps_ms[k] += v
         except abi.AmrError as e:  # atomic refusal: the mesh is unchanged
             if e.code != abi.AMR_ERR_CAPACITY:
                 raise
@@ -89,6 +92,8 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     tot_u = tot_ms = tot_adapt = 0.0
+    for k in steps_ms:
+        steps_ms[k] = 0.0
     for i in range(steps):
         u, ms, ams, counts = one_period()
         tot_u += u
@@ -96,6 +101,7 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
         tot_adapt += ams
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    adapt_steps = {k: round(v / steps, 3) for k, v in steps_ms.items()}
     log("[%s] timed %d steps: %.1f MLUPS (advance), %.2f ms adapt/cycle, wall %.3f s, blocks/level %s" %
         (storage, steps, tot_u / tot_ms / 1e3, tot_adapt / steps, wall, g.counts().tolist()))
     # kernel event timing of the dominant kernel, on the handle's stream
@@ -108,6 +114,7 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
         "mlups_wall": tot_u / wall / 1e6,
         "adv_ms_per_step": tot_ms / steps,
         "adapt_ms_per_cycle": tot_adapt / steps,
+        "adapt_steps_device_ms": adapt_steps,
         "wall_s": wall,
         "level_blocks": g.counts().tolist(),
         "kernels": {k: {"launches": int(v[0]), "ms": v[1], "blocks": v[2], "bytes": v[3]} for k, v in ks.items()},
@@ -430,6 +437,7 @@ def main():
             "level_blocks_end": r32["level_blocks"],
         },
         "adapt_ms_per_cycle": round(r32["adapt_ms_per_cycle"], 3),
+        "adapt_steps_device_ms": r32["adapt_steps_device_ms"],
         "mlups_incl_adapt": round(r32["mlups_wall"], 1),
         "roofline": roofline(r32, "k_collide_stream<27, F32S>"),
         "kernels_f32s": kernel_rates(r32),

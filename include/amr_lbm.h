@@ -119,12 +119,30 @@ typedef struct {
 #define AMR_TAG_COARSEN (-1)
 #define AMR_TAG_REFINE_PERM 2
 
+/* Device time of each adaptation step (the paper's breakdown of the
+ * refinement and coarsening routine, Sec. "Refinement and Coarsening" and its
+ * timing tables), in amr_adapt_stats.step_ms.  The first three are those of
+ * the last amr_tag call on the handle. */
+enum amr_adapt_step {
+    AMR_T_SYNC_AVERAGE = 0,  /* pre-adaptation averaging of every parent (amr_tag) */
+    AMR_T_SYNC_INTERP = 1,   /* pre-adaptation ghost interpolation (amr_tag) */
+    AMR_T_CRITERION = 2,     /* velocities, criterion, block maxima, tags (amr_tag) */
+    AMR_T_PREP = 3,          /* effective tags and their counts */
+    AMR_T_ASSIGN = 4,        /* S2-S3: first-child IDs from the gap stack, 2:1 reversion */
+    AMR_T_BUILD = 5,         /* S4-S6: new children, removals, ID-set compaction and append */
+    AMR_T_CONNECT = 6,       /* S8: links and neighbour-children, cell masks, work lists */
+    AMR_T_FILL = 7,          /* S7: every cell of the new children, neighbours' refreshed slots */
+    AMR_T_STEPS = 8
+};
+
 typedef struct {
     int32_t n_refine;         /* blocks refined */
     int32_t n_coarsen;        /* blocks whose children were removed */
     int32_t n_reverted;       /* coarsen marks reverted by 2:1 balance */
     int32_t n_free;           /* gap-stack size after the call */
     int32_t level_blocks[8];  /* active blocks per level after the call */
+    double step_ms[8];        /* device milliseconds per step, indexed by amr_adapt_step; the
+                                 adaptation steps are 0 when nothing was refined or coarsened */
 } amr_adapt_stats;
 
 typedef struct amr_handle amr_t;

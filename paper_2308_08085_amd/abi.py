@@ -51,7 +51,10 @@ class TagParams(C.Structure):
 
 class AdaptStats(C.Structure):
     _fields_ = [("n_refine", C.c_int32), ("n_coarsen", C.c_int32), ("n_reverted", C.c_int32),
-                ("n_free", C.c_int32), ("level_blocks", C.c_int32 * 8)]
+                ("n_free", C.c_int32), ("level_blocks", C.c_int32 * 8), ("step_ms", C.c_double * 8)]
+
+
+ADAPT_STEPS = ("sync_average", "sync_interp", "criterion", "prep", "assign", "build", "connect", "fill")
 
 
 class BatchTuning(C.Structure):
@@ -199,7 +202,8 @@ class AmrLbm:
         st = AdaptStats()
         _check(load().amr_adapt(self._h, C.byref(st)))
         return {"n_refine": st.n_refine, "n_coarsen": st.n_coarsen, "n_reverted": st.n_reverted,
-                "n_free": st.n_free, "level_blocks": list(st.level_blocks)[: self.lmax]}
+                "n_free": st.n_free, "level_blocks": list(st.level_blocks)[: self.lmax],
+                "step_ms": dict(zip(ADAPT_STEPS, list(st.step_ms)))}
 
     def n_out(self) -> int:
         return int(self._fields(AMR_GET, F_N_OUT, np.zeros(1, np.int64))[0])

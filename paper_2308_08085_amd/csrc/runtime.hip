@@ -409,6 +409,8 @@ amr_status amr_destroy(amr_t *h) {
         hipEventDestroy(t.b);
     }
     for (auto e : h->event_pool) hipEventDestroy(e);
+    for (auto e : h->step_ev)
+        if (e) hipEventDestroy(e);
     delete h;
     return AMR_OK;
 }
@@ -464,6 +466,19 @@ amr_status lbm_step(amr_t *h, int32_t n, uint32_t flags) {
     return AMR_OK;
 }
 
+// event k of the adaptation-step timings, recorded on the handle's stream
+static amr_status mark(amr_handle *h, int k) {
+    if (!h->step_ev[k]) HIP_TRY(hipEventCreate(&h->step_ev[k]));
+    HIP_TRY(hipEventRecord(h->step_ev[k], h->c.stream));
+    return AMR_OK;
+}
+
+// milliseconds between two recorded events (the stream has been synchronised)
+static double between(const amr_handle *h, int a, int b) {
+    float ms = 0.f;
+    return hipEventElapsedTime(&ms, h->step_ev[a], h->step_ev[b]) == hipSuccess ? double(ms) : 0.0;
+}
+
 amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int8_t *tags_out) {
     if (!h) return fail(AMR_ERR_ARG, "handle is NULL");
     if (!tags_in && !p) return fail(AMR_ERR_ARG, "criterion parameters are NULL");
@@ -473,10 +488,14 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
         return fail(AMR_ERR_ARG, "n_start and n_inc must be finite");
     Ctx &c = h->c;
     const size_t cap = (size_t)c.m.cap;
+    amr_status ms;
+    if ((ms = mark(h, 0)) != AMR_OK) return ms;
     // pre-adaptation synchronisation
     for (int L = h->lmax - 2; L >= 0; L--) launch_average(c, c.ids + L * cap, h->nids[L], level_params(h), 1);
+    if ((ms = mark(h, 1)) != AMR_OK) return ms;
     for (int L = 0; L <= h->lmax - 2; L++)
         if (h->niface[L] > 0) launch_interp(c, c.iface + L * cap, h->niface[L], level_params(h), 0);
+    if ((ms = mark(h, 2)) != AMR_OK) return ms;
     launch_crit_reset(c);
     if (tags_in) {
         HIP_TRY(hipMemcpyAsync(c.m.tag, tags_in, cap, hipMemcpyHostToDevice, c.stream));
@@ -499,22 +518,32 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
         launch_tag_distance(c, p->d_spec, p->freeze);
     }
     launch_effective_tags(c);
+    if ((ms = mark(h, 3)) != AMR_OK) return ms;
     if (tags_out) HIP_TRY(hipMemcpyAsync(tags_out, c.m.tag, cap, hipMemcpyDeviceToHost, c.stream));
-    return sync_checked(h);
+    const amr_status s = sync_checked(h);
+    if (s != AMR_OK) return s;
+    for (int k = 0; k < 3; k++) h->step_ms[AMR_T_SYNC_AVERAGE + k] = between(h, k, k + 1);
+    return AMR_OK;
 }
 
 amr_status amr_adapt(amr_t *h, amr_adapt_stats *stats) {
     if (!h) return fail(AMR_ERR_ARG, "handle is NULL");
     Ctx &c = h->c;
+    amr_status s;
+    if ((s = mark(h, 4)) != AMR_OK) return s;
     launch_effective_tags(c);
+    if ((s = mark(h, 5)) != AMR_OK) return s;
     DevCounters dc;
-    amr_status s = read_counters(h, &dc);
+    s = read_counters(h, &dc);
     if (s != AMR_OK) return s;
     const int n_ref = dc.n_ref, n_coa = dc.n_coa;
+    for (int k = AMR_T_PREP; k < AMR_T_STEPS; k++) h->step_ms[k] = 0.0;
+    h->step_ms[AMR_T_PREP] = between(h, 4, 5);
     if (stats) {
         memset(stats, 0, sizeof(*stats));
         stats->n_free = dc.gtop;
         for (int L = 0; L < h->lmax; L++) stats->level_blocks[L] = h->nids[L];
+        for (int k = 0; k < AMR_T_STEPS; k++) stats->step_ms[k] = h->step_ms[k];
     }
     if (n_ref == 0 && n_coa == 0) return AMR_OK;
     if ((long long)c.nc * n_ref > dc.gtop)
@@ -523,17 +552,23 @@ amr_status amr_adapt(amr_t *h, amr_adapt_stats *stats) {
     // blocks are created and removed: the momentum-exchange sums restart
     launch_force_reset(c);
     for (int L = 0; L < kMaxLevels; L++) h->force_sweeps[L] = 0.0;
+    if ((s = mark(h, 6)) != AMR_OK) return s;
     launch_adapt_assign(c, n_ref);
+    if ((s = mark(h, 7)) != AMR_OK) return s;
     launch_adapt_build(c, n_ref);
+    if ((s = mark(h, 8)) != AMR_OK) return s;
     launch_connectivity(c, c.m.cap);
+    if ((s = mark(h, 9)) != AMR_OK) return s;
     // S7: every cell of the new children from their parents' data; after the
     // connectivity rebuild, since populations are stored by their source cell
     if (n_ref > 0) {
         launch_interp(c, c.rlist, n_ref, lp, 1);
         launch_refresh_neighbours(c, c.rlist, n_ref, lp);
     }
+    if ((s = mark(h, 10)) != AMR_OK) return s;
     s = sync_checked(h);
     if (s != AMR_OK) return s;
+    for (int k = 0; k < 4; k++) h->step_ms[AMR_T_ASSIGN + k] = between(h, 6 + k, 7 + k);
     s = read_counters(h, &dc);
     if (s != AMR_OK) return s;
     s = refresh_counts(h);
@@ -545,6 +580,7 @@ amr_status amr_adapt(amr_t *h, amr_adapt_stats *stats) {
         stats->n_reverted = dc.n_rev;
         stats->n_free = dc.gtop;
         for (int L = 0; L < h->lmax; L++) stats->level_blocks[L] = h->nids[L];
+        for (int k = 0; k < AMR_T_STEPS; k++) stats->step_ms[k] = h->step_ms[k];
     }
     return AMR_OK;
 }

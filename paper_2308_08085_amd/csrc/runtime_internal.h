@@ -54,6 +54,11 @@ struct amr_handle {
     std::vector<Timed> timed;
     std::vector<hipEvent_t> event_pool;
     double kstats[3][4] = {{0}};
+    // device times of the adaptation steps (amr_adapt_step order): events at
+    // the step boundaries, read after the stream synchronisations the calls
+    // make anyway; the first three are those of the last amr_tag
+    hipEvent_t step_ev[11] = {nullptr};  // tag: 0-3; adapt: 4-5 (prep), 6-10 (S2 ... S7)
+    double step_ms[AMR_T_STEPS] = {0};
 };
 
 namespace amr {

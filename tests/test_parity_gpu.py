@@ -313,3 +313,25 @@ def test_force_switch_skips_the_exchange_and_keeps_the_fields():
     a.step(2, graph=True)
     assert np.array_equal(c.force(), a.force())  # c accumulated only these two steps
     bt.close()
+
+
+def test_adaptation_step_times_are_reported():
+    """amr_adapt_stats.step_ms: device time of every adaptation step"""
+    case = _cav(3, 19, lmax=3, storage="f32s")
+    g = abi.AmrLbm(case)
+    g.set_root_rho_u(case.initial_rho_u())
+    g.step(20)
+    g.tag(abi.TAG_VORTICITY_REL, theta=0.1)
+    st = g.adapt()
+    ms = st["step_ms"]
+    print("adaptation steps (ms):", ms, flush=True)
+    assert st["n_refine"] > 0
+    assert set(ms) == set(abi.ADAPT_STEPS)
+    assert all(v >= 0.0 for v in ms.values())
+    for k in ("sync_average", "criterion", "prep", "assign", "build", "connect", "fill"):
+        assert ms[k] > 0.0, k
+    # nothing tagged: the adaptation steps are zero, the tag's steps are still timed
+    g.tag(tags_in=np.zeros(case.cap, np.int8))
+    st = g.adapt()
+    assert st["n_refine"] == 0 and st["step_ms"]["build"] == 0.0 and st["step_ms"]["criterion"] >= 0.0
+    g.close()
