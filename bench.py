@@ -40,7 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # dispatch), each scaled by what the counter reads for a 1 GiB copy
 # (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Must be measured
 # again whenever the kernel changes.
-MEASURED_TRAFFIC = {"k_collide_stream<27, F32S>": (1857239.49 * 2.0 + 3050592.42 * 1.0) * 1024}
+MEASURED_TRAFFIC = {"k_collide_stream<27, F32S>": (1857239.49 * 2.0 + 3050592.42 * 1.0) * 1024,
+                    "k_collide_stream<27, F16S>": (920338.09 * 2.0 + 1532091.68 * 1.0) * 1024}
 
 
 def log(*a):
