@@ -255,12 +255,64 @@ def kernel_rates(res):
     return out
 
 
+def copy_bandwidth(gib=1, reps=10):
+    """GB/s (read + write) of a device-to-device copy of `gib` GiB, the practical
+    bandwidth ceiling on this machine"""
+    import torch
+    a = torch.empty(gib << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
+COPY_GBS = [None]  # measured once per run
+
+
+def uniform_sweep(steps=20):
+    """the collide-stream kernel on one uniform periodic level of 384^3 cells
+    (D3Q19, FP32 shifted: 4.3 GB per buffer, over 4 x the 256 MB Infinity Cache)"""
+    import torch
+    from paper_2308_08085_amd import abi, workloads as W
+
+    case = dataclasses.replace(W.cavity(3, 19, 384, 1, 1000.0, storage="f32s", seed=2308092, cap=96 ** 3),
+                               periodic=(1, 1, 1))
+    g = abi.AmrLbm(case)
+    g.set_root_rho_u(case.initial_rho_u())
+    g.step(3, graph=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    g.step(steps, graph=True)
+    e1.record(g.stream)
+    g.synchronize()
+    mlups = steps * case.nroot * 64 / (e0.elapsed_time(e1) * 1e-3) / 1e6
+    g.kernel_stats(reset=True)
+    g.step(steps, profile=True)
+    n, ms, blocks, byts = g.kernel_stats()["collide_stream"]
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    res = {"kernels": {"collide_stream": {"launches": n, "ms": ms, "blocks": blocks, "bytes": byts}}}
+    return {"workload": "uniform periodic D3Q19 level, 384^3 cells (96^3 blocks), FP32 shifted storage",
+            "mlups": round(mlups, 1), "roofline": roofline(res, "k_collide_stream<19, F32S>")}
+
+
 def roofline(res, kernel):
     k = res["kernels"]["collide_stream"]
     gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
     traffic = MEASURED_TRAFFIC.get(kernel)
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic) if traffic else None,
+            "copy_GBs": round(COPY_GBS[0], 1) if COPY_GBS[0] else None,
+            "frac_of_copy": round(gbs / COPY_GBS[0], 4) if COPY_GBS[0] else None,
             "traffic_over_algorithmic": round(traffic * max(k["launches"], 1) / k["bytes"], 3) if traffic else None,
             "kernel": kernel,
             "avg_launch_us": round(k["ms"] * 1e3 / max(k["launches"], 1), 2),
@@ -332,7 +384,13 @@ def cpu_baseline(theta, seconds=20.0):
             o.tag(kind=0, theta=theta)
             o.adapt()
             adapt_s = time.perf_counter() - t0
-    return {"value": round(tot_u / tot_s / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    return {"value": round(tot_u / tot_s / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle", "cpu": model,
             "adapt_ms_per_cycle": round(adapt_s * 1e3, 1) if adapt_s else None,
             "sample": "same cylinder set-up, FP64 oracle, one thread: %d coarse steps from the initial field "
                       "with one vorticity adaptation after step 2 (%.1f s of stepping)" % (n, tot_s)}
@@ -348,6 +406,7 @@ def main():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-cavity", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--no-extensions", action="store_true")
     ap.add_argument("--physics", action="store_true",
                     help="only the paper's square-cylinder runs: C_D and St against its table")
@@ -395,6 +454,8 @@ def main():
 
     abi.load()
     log("device:", torch.cuda.get_device_name(0))
+    COPY_GBS[0] = copy_bandwidth()
+    log("[copy] 1 GiB device-to-device: %.1f GB/s" % COPY_GBS[0])
     main_case = W.config4(cap=W.config4().nroot * 16)
     cav = W.config2()
     theta = main_case.theta
@@ -414,6 +475,9 @@ def main():
                                          "adapt_ms_per_cycle": round(rl["adapt_ms_per_cycle"], 3),
                                          "adaptations_refused_for_capacity": rl["adaptations_refused_for_capacity"],
                                          "level_blocks_end": rl["level_blocks"]}}
+    uni = None if args.no_uniform else uniform_sweep()
+    if uni:
+        log("[uniform] %s: %.1f MLUPS, collide %.1f GB/s" % (uni["workload"], uni["mlups"], uni["roofline"]["achieved"]))
     bat = None if args.no_batch else run_batch(max(2, args.steps // 2), 2, theta)
     err = None if args.no_error_leg else error_leg(theta)
     cpu = None if args.no_cpu_baseline else cpu_baseline(theta)
@@ -459,6 +523,8 @@ def main():
             line["cavity_d3q19"]["speedup_f16s_vs_f32s"] = round(c16["mlups"] / c32["mlups"], 3)
     if ext is not None:
         line["extensions"] = ext
+    if uni is not None:
+        line["uniform_d3q19"] = uni
     if bat is not None:
         line["batched_cfg5"] = bat
     if err is not None:
