@@ -322,12 +322,14 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
     }
 }
 
-// Workgroup size: 16-bit storages use 512 threads, so that in 3-D eight
-// consecutive blocks of the Morton launch order (usually the eight children of
-// one parent) share a CU and its L1; their rows are half as wide and the
-// neighbour reads hit L1 more often.  Wider storages use 256.
+// Workgroup size: 256 threads (3-D: four blocks of the Morton launch order)
+// for every storage.  Boundary and interface blocks take the slower generic
+// path, and a CU can start a new workgroup only when all of its waves fit: with
+// 512 threads a slow wave held back seven others (16-bit storage on the
+// cylinder set-up: 968 us per launch against 915 us with 256), while 128
+// threads lose the neighbour reuse between the blocks of a workgroup.
 template <int S>
-constexpr int collide_threads() { return sizeof(typename Store<S>::T) <= 2 ? 512 : 256; }
+constexpr int collide_threads() { return 256; }
 
 template <int Q, int S, bool NTS>
 __global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
