@@ -88,8 +88,8 @@ __host__ __device__ inline int region_of(int x, int y, int z) {
 template <typename Dd> constexpr int kCenterSlot = Dd::D == 2 ? 4 : 13;
 
 // ---------------------------------------------------------------------------
-// Storage formats.  Shifted forms keep g = f - w; arithmetic in R.
-// Storage formats.  stnt is a non-temporal store: a collide-stream sweep's
+// Storage formats.  Shifted forms keep g = f - w; arithmetic in R.  stnt is a
+// non-temporal store: a collide-stream sweep's
 // output is read only by the next sweep, after the whole level has streamed
 // through the caches, so keeping it out of L2 leaves room there for the
 // neighbour rows that the gather reads twice.

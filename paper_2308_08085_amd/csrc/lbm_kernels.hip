@@ -83,6 +83,36 @@ __device__ __forceinline__ void gather_cell(const DevMesh &m, const int32_t *lin
     for (int p = 0; p < Lt::Q; p++) g[p] = load_g<Lt, ST>(f, entry_slot<Lt>(m, link, B, h, p, l), p);
 }
 
+// The same for a block whose only links outside the fluid are domain faces or
+// solid blocks (no coarser neighbour): each population comes from a same-level
+// block or from the cell's own opposite slot, a select between two addresses
+// rather than a branch per population.
+template <typename Lt, typename ST>
+__device__ __forceinline__ void gather_cell_nohalo(const DevMesh &m, const int32_t *link, int B, int l,
+                                                   const typename ST::T *f, typename ST::R *g) {
+#pragma unroll
+    for (int p = 0; p < Lt::Q; p++) {
+        const int sx = (l & 3) - Lt::cx(p), sy = ((l >> 2) & 3) - Lt::cy(p), sz = (l >> 4) - Lt::cz(p);
+        const int32_t code = link[region_of<Lt>(sx, sy, sz)];
+        const bool in = code >= 0 && code < m.cap;
+        const int blk = in ? code : B;
+        const int q = in ? p : Lt::opp(p);
+        const int cell = in ? (sx & 3) + 4 * (sy & 3) + 16 * (sz & 3) : l;
+        g[p] = load_g<Lt, ST>(f, mslot<Lt>(blk, q, cell), p);
+    }
+}
+
+// gather of a cell of a block with flags `flag`: the select form unless the
+// block has a coarser neighbour
+template <typename Lt, typename ST>
+__device__ __forceinline__ void gather_cell_flag(const DevMesh &m, const int32_t *link, int B, int h, uint8_t flag,
+                                                 int l, const typename ST::T *f, typename ST::R *g) {
+    if (flag & BF_NSKIP)
+        gather_cell<Lt, ST>(m, link, B, h, l, f, g);
+    else
+        gather_cell_nohalo<Lt, ST>(m, link, B, l, f, g);
+}
+
 template <typename Lt, typename ST>
 __device__ __forceinline__ void scatter_cell(const DevMesh &m, const int32_t *link, int B, int h, int l,
                                              typename ST::T *f, const typename ST::R *g) {
@@ -482,7 +512,7 @@ __device__ __forceinline__ void interp_parent(const DevMesh &m, int P, const typ
     stage_blocks<Lt, NC + 1>(m, sm.st);
     if (t < MB) {
         R g[Q];
-        gather_cell<Lt, ST>(m, sm.st.link[NC], P, sm.st.hid[NC], t, src, g);
+        gather_cell_flag<Lt, ST>(m, sm.st.link[NC], P, sm.st.hid[NC], sm.st.flag[NC], t, src, g);
         R drho, ux, uy, uz;
         moments_g<Lt, R>(g, drho, ux, uy, uz);
         const R uu = ux * ux + uy * uy + uz * uz;
@@ -693,7 +723,7 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, const ty
     const int lead = lf & ~(Lt::D == 3 ? 0x15 : 0x5);
     R g[Q];
     if ((im >> lead) & 1ull) {
-        gather_cell<Lt, ST>(m, st.link[c], child, st.hid[c], lf, src, g);
+        gather_cell_flag<Lt, ST>(m, st.link[c], child, st.hid[c], st.flag[c], lf, src, g);
     } else {
 #pragma unroll
         for (int p = 0; p < Q; p++) g[p] = R(0);
