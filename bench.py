@@ -512,6 +512,7 @@ def main():
         line["fp16s"] = {"mlups": round(r16["mlups"], 1), "adapt_ms_per_cycle": round(r16["adapt_ms_per_cycle"], 3),
                          "speedup_vs_fp32": round(r16["mlups"] / r32["mlups"], 3),
                          "roofline": roofline(r16, "k_collide_stream<27, F16S>"),
+                         "kernels": kernel_rates(r16),
                          "level_blocks_end": r16["level_blocks"]}
     if c32 is not None:
         line["cavity_d3q19"] = {
