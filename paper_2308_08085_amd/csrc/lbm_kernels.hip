@@ -683,11 +683,13 @@ __global__ void k_clear_fresh(const int32_t *__restrict__ list, int n, DevMesh m
 // Fine-to-coarse averaging with rescaling (Sec. "Averaging"): parent cell
 // (i,j,k) takes the mean of the 2^d rescaled cells of child octant
 // (i/2, j/2, k/2) starting at fine cell (2(i mod 2), 2(j mod 2), 2(k mod 2)).
-// One workgroup per parent, one lane per fine cell of its children (3-D: a
-// wave per child): every lane gathers and rescales its cell, the 2^d cells of
-// a parent cell (lanes differing in bits 0, 2, 4 of the cell index) are summed
-// with xor shuffles, and the lane of the first one writes the parent cell.
-// Children without a targeted cell are skipped whole.
+// One lane per fine cell of the children (3-D: a wave per child; two
+// workgroups of four children per parent, so that children that end early do
+// not hold back a workgroup of eight): every lane gathers and rescales its
+// cell, the 2^d cells of a parent cell (lanes differing in bits 0, 2, 4 of the
+// cell index, all in one wave) are summed with xor shuffles, and the lane of
+// the first one writes the parent cell.  Children without a targeted cell are
+// skipped whole.
 
 // refined parents with children in the next level
 __device__ inline bool average_target(const DevMesh &m, int P, int nc) {
@@ -700,20 +702,26 @@ __device__ __forceinline__ R xor_sum(R v, int mask) {
     return v + __shfl_xor(v, mask, 64);
 }
 
+// children per averaging workgroup
+template <int Q>
+constexpr int avg_children() { return Lat<Q>::D == 3 ? 4 : Lat<Q>::NC; }
+
+// children c0 .. c0 + NCW - 1 of parent P
 template <int Q, int S>
-__device__ __forceinline__ void average_parent(const DevMesh &m, int P, const typename Store<S>::T *src,
+__device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, const typename Store<S>::T *src,
                                                typename Store<S>::T *dst, typename Store<S>::R r, int all_cells,
-                                               BlockStage<Lat<Q>, Lat<Q>::NC + 1> &st, int t) {
+                                               BlockStage<Lat<Q>, avg_children<Q>() + 1> &st, int t) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
-    constexpr int MB = Lt::MB, NC = Lt::NC;
+    constexpr int MB = Lt::MB, NCW = avg_children<Q>(), NC = Lt::NC;
     const int first = m.nbrc[P];
-    if (t <= NC) st.id[t] = t < NC ? first + t : P;
+    if (t <= NCW) st.id[t] = t < NCW ? first + c0 + t : P;
     __syncthreads();
-    stage_blocks<Lt, NC + 1>(m, st);
-    const int c = t / MB, lf = t - c * MB;
-    if (c >= NC) return;
+    stage_blocks<Lt, NCW + 1>(m, st);
+    const int cw = t / MB, lf = t - cw * MB;
+    if (cw >= NCW) return;
+    const int c = c0 + cw;  // octant of the child in its parent
     const int child = first + c;
     const uint64_t im = all_cells ? ~0ull : m.imask[child];
     if (im == 0) return;  // the whole child (a wave in 3-D, a 16-lane group in 2-D)
@@ -723,7 +731,7 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, const ty
     const int lead = lf & ~(Lt::D == 3 ? 0x15 : 0x5);
     R g[Q];
     if ((im >> lead) & 1ull) {
-        gather_cell_flag<Lt, ST>(m, st.link[c], child, st.hid[c], st.flag[c], lf, src, g);
+        gather_cell_flag<Lt, ST>(m, st.link[cw], child, st.hid[cw], st.flag[cw], lf, src, g);
     } else {
 #pragma unroll
         for (int p = 0; p < Q; p++) g[p] = R(0);
@@ -743,50 +751,54 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, const ty
     const int i = lf & 3, j = (lf >> 2) & 3, k = lf >> 4;
     if (lf != lead || !((im >> lf) & 1ull)) return;
     const int l = ((c & 1) * 2 + (i >> 1)) + 4 * (((c >> 1) & 1) * 2 + (j >> 1)) + 16 * ((c >> 2) * 2 + (k >> 1));
-    const int32_t *plink = st.link[NC];
-    const int ph = st.hid[NC];
+    const int32_t *plink = st.link[NCW];
+    const int ph = st.hid[NCW];
 #pragma unroll
     for (int p = 0; p < Q; p++) store_g<Lt, ST>(dst, entry_slot<Lt>(m, plink, P, ph, p, l), p, g[p] / R(NC));
 }
 
+// grid: NC / avg_children workgroups per listed parent
 template <int Q, int S>
-__global__ __launch_bounds__(512) void k_average(const int32_t *__restrict__ list, int n, DevMesh m,
+__global__ __launch_bounds__(256) void k_average(const int32_t *__restrict__ list, int n, DevMesh m,
                                                  typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
                                                  int all_cells) {
     using Lt = Lat<Q>;
     using R = typename Store<S>::R;
-    __shared__ BlockStage<Lt, Lt::NC + 1> st;
-    if ((int)blockIdx.x >= n) return;
-    const int P = list[blockIdx.x];
+    constexpr int SPLIT = Lt::NC / avg_children<Q>();
+    __shared__ BlockStage<Lt, avg_children<Q>() + 1> st;
+    const int item = blockIdx.x / SPLIT, part = blockIdx.x % SPLIT;
+    if (item >= n) return;
+    const int P = list[item];
     if (!average_target(m, P, Lt::NC)) return;
     const int L = m.level[P];
-    average_parent<Q, S>(m, P, lp.par[L + 1] ? f1 : f0, lp.par[L] ? f1 : f0, R(lp.r_fc[L]), all_cells, st,
-                         threadIdx.x);
+    average_parent<Q, S>(m, P, part * avg_children<Q>(), lp.par[L + 1] ? f1 : f0, lp.par[L] ? f1 : f0,
+                         R(lp.r_fc[L]), all_cells, st, threadIdx.x);
 }
 
 // Batched interface averaging of level L+1 into level L, persistent
 // workgroups; par0/par1 = buffers of levels L, L+1.
 template <int Q, int S>
-__global__ __launch_bounds__(512) void k_average_batch(const SimDesc *__restrict__ sims,
+__global__ __launch_bounds__(256) void k_average_batch(const SimDesc *__restrict__ sims,
                                                        const uint32_t *__restrict__ items,
                                                        const int32_t *__restrict__ count, int L, int par0, int par1) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
     using T = typename ST::T;
-    __shared__ BlockStage<Lt, Lt::NC + 1> st;
+    constexpr int SPLIT = Lt::NC / avg_children<Q>();
+    __shared__ BlockStage<Lt, avg_children<Q>() + 1> st;
     int u0, u1;
-    persistent_range(*count, u0, u1);
+    persistent_range(*count * SPLIT, u0, u1);
     for (int u = u0; u < u1; u++) {
         int sim, P;
-        decode_item(items[u], sim, P);
+        decode_item(items[u / SPLIT], sim, P);
         sim = __builtin_amdgcn_readfirstlane(sim);  // one item per workgroup
         P = __builtin_amdgcn_readfirstlane(P);
         CSimDesc *cs = const_view(sims) + sim;
         const DevMesh m = load_mesh(cs);
         if (average_target(m, P, Lt::NC))
-            average_parent<Q, S>(m, P, (const T *)cs->f[par1], (T *)cs->f[par0], R(cs->lp.r_fc[L]), 0, st,
-                                 opaque_tid());
+            average_parent<Q, S>(m, P, (u % SPLIT) * avg_children<Q>(), (const T *)cs->f[par1], (T *)cs->f[par0],
+                                 R(cs->lp.r_fc[L]), 0, st, opaque_tid());
         __syncthreads();
     }
 }
@@ -1368,7 +1380,7 @@ void launch_interp_batch(hipStream_t stream, int q, int storage, const SimDesc *
 
 void launch_average_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,
                           const int32_t *count, int L, int par0, int par1, int grid) {
-    const int threads = q == 9 ? 64 : 512;  // one lane per fine cell of the children
+    const int threads = q == 9 ? 64 : 256;  // one lane per fine cell of the workgroup's children
     AMR_DISPATCH(q, storage,
                  (k_average_batch<Qc, Sc><<<grid, threads, 0, stream>>>(sims, items, count, L, par0, par1)));
 }
@@ -1391,10 +1403,12 @@ void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const L
 
 void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {
     if (n <= 0) return;
-    const int threads = c.nc * c.mb;  // one lane per fine cell of the children
+    // one lane per fine cell of the workgroup's children; 3-D: two workgroups per parent
+    const int split = c.dim == 3 ? 2 : 1;
+    const int threads = c.nc / split * c.mb;
     AMR_DISPATCH(c.q, c.storage,
-                 (k_average<Qc, Sc><<<n, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]),
-                                                                 lp, all_cells)));
+                 (k_average<Qc, Sc><<<n * split, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]),
+                                                                         TPTR(Sc, c.f[1]), lp, all_cells)));
 }
 
 void launch_fill_rest(const Ctx &c) {
