@@ -168,7 +168,8 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
  * ineligible tags are dropped: refinement only of leaves below level L_max-1
  * with no N_SKIP link (2:1 balance), coarsening only of blocks with status
  * AMR_ST_REFINED.  tags_out (host, max_blocks, nullable) receives the
- * effective tags.  Synchronises the stream.
+ * effective tags.  Synchronises the stream.  The device times of the
+ * synchronisation and the criterion are kept for the next amr_adapt's stats.
  * Errors: AMR_ERR_ARG, AMR_ERR_DEVICE. */
 amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int8_t *tags_out);
 
@@ -179,7 +180,8 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
  * parent ID, child) order; ID sets drop removed IDs stably and append new
  * children in (parent ID, child) order; new children are interpolated from
  * their parents; neighbour and neighbour-child tables are rebuilt.  Consumes
- * the tags of the last amr_tag.  `stats` (host, nullable) receives counts.
+ * the tags of the last amr_tag.  `stats` (host, nullable) receives counts and
+ * the device time of each step (amr_adapt_step).
  * Errors: AMR_ERR_CAPACITY when the gap stack cannot hold the new children
  * (nothing changed), AMR_ERR_DEVICE. */
 amr_status amr_adapt(amr_t *h, amr_adapt_stats *stats);
