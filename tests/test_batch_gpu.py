@@ -150,3 +150,57 @@ def test_batch_refuses_bad_members():
         b.step(1)
     assert e.value.code == abi.AMR_ERR_STATE
     b.close()
+
+
+def test_benchmark_batch_sampled_cells_match_the_oracle():
+    """The 64-member batch of the benchmark (FP16 shifted storage), one fused
+    graph-replayed coarse step in the concurrent-groups schedule: before any
+    adaptation every member is one level, so an interior block's new f_p(x) is
+    population p of the oracle's BGK collision of the pre-step populations at
+    x - c_p.  Two 2-D and two 3-D members, 16 blocks each, every cell."""
+    import oracle
+    from meshcheck import block_vectors
+
+    cases = W.config5_cases()
+    shared = torch.cuda.Stream()
+    sims = make(cases, stream=shared)
+    b = abi.AmrBatch(sims)
+    b.set_tuning(256, 8, 1)
+    picks = [0, 1, 32, 33]
+    rng = np.random.default_rng(20230808)
+    pre = {}
+    for i in picks:
+        c, g = cases[i], sims[i]
+        nbr = g.mesh()["nbr"]
+        blocks = np.flatnonzero(np.all(nbr[: c.nroot] >= 0, axis=1))
+        sample = rng.choice(blocks, min(16, len(blocks)), replace=False)
+        pre[i] = (sample, g.get_block_f_all(), nbr)
+    b.step(1, graph=True)
+    for i in picks:
+        c, g = cases[i], sims[i]
+        sample, f, nbr = pre[i]
+        d, q = c.dim, c.q
+        cv, w, _ = oracle.lattice(d, q)
+        vec = np.array(block_vectors(d))
+        omega = 1.0 / (3.0 * c.nu0 + 0.5)
+        got = g.get_block_f_all()[sample]
+        n = 12 if d == 3 else 1
+        for s_, B in enumerate(sample):
+            # the block and its neighbours as a 12^d region, cell-major
+            region = np.zeros((n, 12, 12, q))
+            for r in range(len(vec)):
+                ox, oy, oz = 4 * (vec[r] + 1)
+                blk = f[nbr[B, r]].reshape((4, 4, 4, q) if d == 3 else (1, 4, 4, q))
+                region[(oz if d == 3 else 0):(oz + 4 if d == 3 else 1), oy:oy + 4, ox:ox + 4] = blk
+            post = {}
+            for l in range(c.mb):
+                i_, j_, k_ = l & 3, (l >> 2) & 3, l >> 4
+                for p in range(q):
+                    y = ((4 + k_ - cv[p, 2]) if d == 3 else 0, 4 + j_ - cv[p, 1], 4 + i_ - cv[p, 0])
+                    if y not in post:
+                        post[y] = oracle.collide(d, q, omega, region[y])
+                    want = post[y][p]
+                    tol = 2.0 ** -11 * abs(want - w[p]) + 2e-7
+                    assert abs(got[s_, l, p] - want) <= tol, (c.name, int(B), l, p, got[s_, l, p], want)
+        print("%s: %d sampled blocks match" % (c.name, len(sample)), flush=True)
+    b.close()
