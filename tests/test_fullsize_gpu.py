@@ -130,14 +130,14 @@ def test_graph_replay_equals_eager_at_full_size():
     assert np.array_equal(runs[0], runs[1])
 
 
-@pytest.mark.parametrize("storage", ["f32s", "f16s"])
-def test_sampled_level0_cells_match_the_oracle_at_full_size(storage):
-    """A level-0 leaf whose 26 neighbours are all fluid blocks advances by one
+def _sampled_level0_check(case, n_blocks=64):
+    """A level-0 leaf whose neighbours are all fluid blocks advances by one
     collide-stream sweep per coarse step (Secs. "Streaming", "Collision"): the
     new f_p(x) is population p of the oracle's BGK collision of the pre-step
-    populations at x - c_p.  64 such blocks, every cell and population, after a
-    graph-replayed coarse step of the full set-up."""
-    case = full_case(storage=storage)
+    populations at x - c_p.  After near-wall refinement and a few steps, every
+    cell and population of n_blocks such blocks after a graph-replayed coarse
+    step; tolerance: half an ulp of the stored shifted value plus 2e-7."""
+    d, q = case.dim, case.q
     t0 = time.perf_counter()
     g = abi.AmrLbm(case)
     g.set_root_rho_u(case.initial_rho_u())
@@ -147,43 +147,56 @@ def test_sampled_level0_cells_match_the_oracle_at_full_size(storage):
     nbr = m["nbr"]
     leaf0 = np.flatnonzero((m["level"] == 0) & (m["status"] == 0))
     inner = leaf0[np.all(nbr[leaf0] >= 0, axis=1)]
-    assert len(inner) > 1000
+    assert len(inner) > 4 * n_blocks
     rng = np.random.default_rng(20230808)
-    # half near the refined region (more structure), half anywhere
+    # half near the cylinder (more structure), half anywhere
     X = m["X"].astype(np.int64)
-    near = inner[np.argsort(np.abs(X[inner, 0] - 64 * 4))[:2000]]
-    sample = np.unique(np.concatenate([rng.choice(near, 32, replace=False), rng.choice(inner, 32, replace=False)]))
-    vec = np.array(block_vectors(3))
-    c, w, _ = oracle.lattice(3, 27)
-    # the block and its 26 neighbours, as a 12^3-cell region per sample
+    # x of the cylinder's first solid block in finest-cell units (4 root cells per block)
+    x_cyl = int(np.flatnonzero(case.solid)[0] % case.root[0]) * 4 * (1 << (case.lmax - 1))
+    near = inner[np.argsort(np.abs(X[inner, 0] - x_cyl))[: 30 * n_blocks]]
+    half = n_blocks // 2
+    sample = np.unique(np.concatenate([rng.choice(near, half, replace=False), rng.choice(inner, half, replace=False)]))
+    vec = np.array(block_vectors(d))
+    c, w, _ = oracle.lattice(d, q)
+    nz = 12 if d == 3 else 1
     f = g.get_block_f_all()
-    region = np.zeros((len(sample), 12, 12, 12, 27))
+    region = np.zeros((len(sample), nz, 12, 12, q))
     for s_, B in enumerate(sample):
-        for r in range(27):
-            N = nbr[B, r]
+        for r in range(len(vec)):
             ox, oy, oz = 4 * (vec[r] + 1)
-            region[s_, oz:oz + 4, oy:oy + 4, ox:ox + 4] = f[N].reshape(4, 4, 4, 27)
+            z0, z1 = (oz, oz + 4) if d == 3 else (0, 1)
+            region[s_, z0:z1, oy:oy + 4, ox:ox + 4] = f[nbr[B, r]].reshape((4 if d == 3 else 1), 4, 4, q)
     del f
     g.step(1, graph=True)
-    got = g.get_block_f_all()[sample].reshape(len(sample), 4, 4, 4, 27)
-    print("full-size %s: %d sampled level-0 blocks, %.1f s" % (storage, len(sample), time.perf_counter() - t0),
-          flush=True)
+    got = g.get_block_f_all()[sample].reshape(len(sample), 4 if d == 3 else 1, 4, 4, q)
     omega = 1.0 / (3.0 * case.nu0 + 0.5)
     want = np.zeros_like(got)
     for s_ in range(len(sample)):
         post = {}
-        for k in range(4):
+        for k in range(4 if d == 3 else 1):
             for j in range(4):
                 for i in range(4):
-                    for p in range(27):
-                        y = (4 + k - c[p, 2], 4 + j - c[p, 1], 4 + i - c[p, 0])
+                    for p in range(q):
+                        y = ((4 + k - c[p, 2]) if d == 3 else 0, 4 + j - c[p, 1], 4 + i - c[p, 0])
                         if y not in post:
-                            post[y] = oracle.collide(3, 27, omega, region[(s_,) + y])
+                            post[y] = oracle.collide(d, q, omega, region[(s_,) + y])
                         want[s_, k, j, i, p] = post[y][p]
-    # storage rounding of the shifted value g = f - w, plus FP32 arithmetic
     gshift = np.abs(want - w)
-    tol = (2.0 ** -11 * gshift + 2e-7) if storage == "f16s" else (2.0 ** -23 * gshift + 2e-7)
+    tol = (2.0 ** -11 * gshift + 2e-7) if case.storage == "f16s" else (2.0 ** -23 * gshift + 2e-7)
     err = np.abs(got - want)
-    print("  max |f - oracle| %.3e, max err / tol %.3f" % (err.max(), (err / tol).max()), flush=True)
+    print("full-size %s %s: %d sampled level-0 blocks, max |f - oracle| %.3e, max err / tol %.3f, %.1f s" %
+          (case.name, case.storage, len(sample), err.max(), (err / tol).max(), time.perf_counter() - t0), flush=True)
     assert np.all(err <= tol)
     g.close()
+
+
+@pytest.mark.parametrize("storage", ["f32s", "f16s"])
+def test_sampled_level0_cells_match_the_oracle_at_full_size(storage):
+    """the D3Q27 cylinder of the benchmark"""
+    _sampled_level0_check(full_case(storage=storage))
+
+
+@pytest.mark.parametrize("storage", ["f32s", "f16s"])
+def test_sampled_level0_cells_match_the_oracle_d2q9_cylinder(storage):
+    """the D2Q9 square cylinder: 1024 x 256 root cells, D = 32, 4 levels"""
+    _sampled_level0_check(W.config3(cap=W.config3().nroot * 12, storage=storage))
