@@ -27,10 +27,11 @@ NONE_ID, N_SKIP, SOLID_CODE = -1, -2, -9
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (``-O2``, plain C99, FP64)."""
+    """Compile the oracle with gcc (``-O2``, plain C99, FP64; OpenMP over the
+    per-block loops, which does not change any result)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -65,7 +66,8 @@ def lib():
                      "orc_tag", "orc_adapt", "orc_get_crit", "orc_get_out", "orc_mass_mom", "orc_get_mesh",
                      "orc_lattice", "orc_feq", "orc_collide", "orc_interp_child", "orc_interp_child_cubic",
                      "orc_average_parent",
-                     "orc_parity", "orc_force"):
+                     "orc_parity", "orc_force", "orc_get_f_all", "orc_cell_classes", "orc_set_threads",
+                     "orc_ratios"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -118,6 +120,11 @@ def average_parent(dim: int, q: int, r: float, children) -> np.ndarray:
     out = np.zeros((mb, q), np.float64)
     lib().orc_average_parent(dim, q, C.c_double(r), _dp(children), _dp(out))
     return out
+
+
+def set_threads(n: int = 0) -> int:
+    """host threads of the oracle's per-block loops (0: leave unchanged); returns the count in use"""
+    return int(lib().orc_set_threads(int(n)))
 
 
 # ---------------------------------------------------------------- forest
@@ -179,6 +186,19 @@ class Oracle:
         f = np.ascontiguousarray(f, np.float64)
         lib().orc_set_block_f(self.h, int(B), _dp(f))
 
+    def get_f_all(self) -> np.ndarray:
+        """[cap][Mb][q]: every active block's current data (zeros for inactive IDs)"""
+        out = np.zeros((self.cap, self.mb, self.q), np.float64)
+        lib().orc_get_f_all(self.h, _dp(out))
+        return out
+
+    def cell_classes(self, B: int) -> np.ndarray:
+        """[Mb]: 0 interior, 1 interface, 2 ghost (Sec. "Grid Communication")"""
+        out = np.zeros(self.mb, np.int32)
+        if lib().orc_cell_classes(self.h, int(B), _ip(out)) != 0:
+            raise ValueError("block %d is not active" % B)
+        return out
+
     def step(self, n: int = 1):
         lib().orc_step(self.h, int(n))
 
@@ -214,6 +234,13 @@ class Oracle:
         out = np.zeros(self.cap, np.float64)
         lib().orc_get_crit(self.h, _dp(out))
         return out
+
+    def ratios(self, L: int):
+        """(coarse-to-fine, fine-to-coarse) rescaling ratios between levels L and L+1"""
+        out = np.zeros(2, np.float64)
+        if lib().orc_ratios(self.h, int(L), _dp(out)) != 0:
+            raise ValueError("no level %d -> %d" % (L, L + 1))
+        return float(out[0]), float(out[1])
 
     def parity(self, L: int) -> int:
         return int(lib().orc_parity(self.h, L))

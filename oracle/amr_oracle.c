@@ -11,11 +11,22 @@
  * readings is kept with the design notes of the repository).  The loops are
  * deliberately naive: one cell, one direction at a time, in the order the
  * paper describes, no blocking or fusion.
+ *
+ * Threads: the per-block loops of a level sweep, of the interpolation, of the
+ * averaging and of the criterion may run on several host threads (OpenMP,
+ * orc_set_threads).  Every block writes only slots no other block writes in
+ * the same loop (a push targets one slot per (cell, direction); the
+ * interpolation writes the children of its own parent; the averaging its own
+ * parent's cells), and no sum crosses blocks, so the results do not depend on
+ * the thread count.
  */
 #include "amr_oracle.h"
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NONE_ID (-1)
 #define N_SKIP (-2)
@@ -359,6 +370,14 @@ static double ratio_fc(const orc_t *o, int L)
     return 2.0 * o->tau[L] / o->tau[L + 1];
 }
 
+int orc_ratios(orc_t *o, int32_t L, double *out2)
+{
+    if (L < 0 || L + 1 >= o->lmax) return -1;
+    out2[0] = ratio_cf(o, L);
+    out2[1] = ratio_fc(o, L);
+    return 0;
+}
+
 /* Root-grid neighbour of root block (bi,bj,bk) in direction p (Sec. "Data
  * Structures": the root grid is structured, so its links are known).  Regions
  * outside the domain get the code of the highest-priority face they cross. */
@@ -493,6 +512,28 @@ int orc_get_block_f(orc_t *o, int32_t B, double *out)
     return 0;
 }
 
+/* every active block's current data, [cap][Mb][q]; inactive blocks read 0 */
+int orc_get_f_all(orc_t *o, double *out)
+{
+    size_t n = (size_t)o->mb * o->q;
+    for (int32_t B = 0; B < o->cap; B++) {
+        if (o->status[B] == ST_INACTIVE) memset(out + B * n, 0, sizeof(double) * n);
+        else memcpy(out + B * n, cellf(o, o->par[o->level[B]], B, 0), sizeof(double) * n);
+    }
+    return 0;
+}
+
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 int orc_set_block_f(orc_t *o, int32_t B, const double *in)
 {
     if (B < 0 || B >= o->cap) return -1;
@@ -523,6 +564,14 @@ static int cell_class(const orc_t *o, int32_t B, int l)
     if (d <= 2) return CLS_GHOST;
     if (d <= 4) return CLS_INTERFACE;
     return CLS_INTERIOR;
+}
+
+/* cell classes of block B (0 interior, 1 interface, 2 ghost), out[Mb] */
+int orc_cell_classes(orc_t *o, int32_t B, int32_t *out)
+{
+    if (B < 0 || B >= o->cap || o->status[B] == ST_INACTIVE) return -1;
+    for (int l = 0; l < o->mb; l++) out[l] = cell_class(o, B, l);
+    return 0;
 }
 
 static int has_nskip(const orc_t *o, int32_t B)
@@ -585,6 +634,7 @@ static void collide_stream_level(orc_t *o, int L)
     double omega = 1.0 / o->tau[L];
     int q = o->q, nb = o->nb;
     o->sweeps[L] += 1.0;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int32_t n = 0; n < o->nids[L]; n++) {
         int32_t B = o->ids[L][n];
         int leaf = o->status[B] == ST_UNREFINED;
@@ -651,6 +701,7 @@ static void interp_parent(orc_t *o, int L, int32_t P, int all_cells)
 
 static void interp_level(orc_t *o, int L)
 {
+#pragma omp parallel for schedule(dynamic, 4)
     for (int32_t n = 0; n < o->nids[L]; n++) {
         int32_t P = o->ids[L][n];
         if (is_refined(o->status[P])) interp_parent(o, L, P, 0);
@@ -664,6 +715,7 @@ static void average_level(orc_t *o, int L, int all_cells)
 {
     int q = o->q, mb = o->mb;
     double r = ratio_fc(o, L);
+#pragma omp parallel for schedule(dynamic, 4)
     for (int32_t n = 0; n < o->nids[L]; n++) {
         int32_t P = o->ids[L][n];
         if (!is_refined(o->status[P])) continue;
@@ -829,7 +881,8 @@ int orc_tag(orc_t *o, const orc_tag_params *prm, const int8_t *tags_in, int8_t *
         memcpy(raw, tags_in, o->cap);
     } else if (prm->kind == 0 || prm->kind == 2) {
         double wmax = 0.0;
-        for (int L = 0; L < o->lmax; L++)
+        for (int L = 0; L < o->lmax; L++) {
+#pragma omp parallel for schedule(dynamic, 16)
             for (int32_t n = 0; n < o->nids[L]; n++) {
                 int32_t B = o->ids[L][n];
                 if (o->status[B] != ST_UNREFINED) continue;
@@ -839,8 +892,10 @@ int orc_tag(orc_t *o, const orc_tag_params *prm, const int8_t *tags_in, int8_t *
                     if (w > m) m = w;
                 }
                 o->crit[B] = m;
-                if (m > wmax) wmax = m;
             }
+        }
+        for (int32_t B = 0; B < o->cap; B++)
+            if (o->crit[B] > wmax) wmax = o->crit[B];
         double thr = prm->theta * wmax;
         double nx = 4.0 * o->cfg.root[0]; /* domain length along x in root cells */
         int8_t *ldes = (int8_t *)calloc(o->cap, 1);

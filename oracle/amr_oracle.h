@@ -72,6 +72,12 @@ int orc_set_root_rho_u(orc_t *o, const double *ru);
 /* copy f of block B (current level buffer), cell-major [Mb*q] */
 int orc_get_block_f(orc_t *o, int32_t B, double *out);
 int orc_set_block_f(orc_t *o, int32_t B, const double *in);
+/* every active block's current data, [cap][Mb][q] cell-major; inactive blocks read 0 */
+int orc_get_f_all(orc_t *o, double *out);
+/* cell classes of an active block: 0 interior, 1 interface, 2 ghost; out[Mb] */
+int orc_cell_classes(orc_t *o, int32_t B, int32_t *out);
+/* host threads of the per-block loops (n <= 0: unchanged); returns the count in use */
+int orc_set_threads(int n);
 int orc_step(orc_t *o, int32_t n_coarse_steps);
 int orc_sync(orc_t *o);
 int orc_tag(orc_t *o, const orc_tag_params *p, const int8_t *tags_in, int8_t *tags_out);
@@ -90,6 +96,8 @@ int orc_mass_mom(orc_t *o, double *out4);
 int orc_get_mesh(orc_t *o, int8_t *level, int8_t *status, int32_t *X3, int32_t *nbr, int32_t *nbrc,
                  int32_t *n_ids, int32_t *ids, int32_t *gtop, int32_t *gap);
 int32_t orc_parity(orc_t *o, int32_t L);
+/* rescaling ratios of level L -> L+1: out2[0] coarse-to-fine, out2[1] fine-to-coarse */
+int orc_ratios(orc_t *o, int32_t L, double *out2);
 
 #ifdef __cplusplus
 }

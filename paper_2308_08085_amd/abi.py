@@ -19,7 +19,7 @@ AMR_ERR_ARG, AMR_ERR_CAPACITY, AMR_ERR_STATE, AMR_ERR_DEVICE, AMR_ERR_UNSTABLE =
 STORAGE = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3, "bf16s": 4}
 AMR_GET, AMR_SET = 0, 1
 (F_N_OUT, F_CELLS, F_RHO_U, F_F, F_BLOCK_F, F_LEVEL, F_STATUS, F_COORD, F_NBR, F_NBR_CHILD, F_IDSET, F_GAP,
- F_COUNTS, F_MASS_MOM, F_CRIT, F_PARITY, F_KERNEL_STATS, F_FORCE, F_FORCE_ON) = range(19)
+ F_COUNTS, F_MASS_MOM, F_CRIT, F_PARITY, F_KERNEL_STATS, F_FORCE, F_FORCE_ON, F_STREAM_BYTES) = range(20)
 AMR_CHECK_FINITE, AMR_USE_GRAPH, AMR_PROFILE = 1, 2, 4
 TAG_VORTICITY_REL, TAG_DISTANCE, TAG_LADDER = 0, 1, 2
 
@@ -241,6 +241,13 @@ class AmrLbm:
         if on is not None:
             self._fields(AMR_SET, F_FORCE_ON, np.array([1 if on else 0], np.int32))
         return bool(self._fields(AMR_GET, F_FORCE_ON, np.zeros(1, np.int32))[0])
+
+    def stream_bytes(self, value=None):
+        """store policy: sweeps writing more than this many bytes use non-temporal
+        stores; with `value`, set it first (0 = every level)"""
+        if value is not None:
+            self._fields(AMR_SET, F_STREAM_BYTES, np.array([int(value)], np.int64))
+        return int(self._fields(AMR_GET, F_STREAM_BYTES, np.zeros(1, np.int64))[0])
 
     def mass_mom(self):
         return self._fields(AMR_GET, F_MASS_MOM, np.zeros(4, np.float64))

@@ -54,8 +54,12 @@ struct Ctx {
     DevCounters *ctr;
     void *staging;
     size_t staging_bytes;
+    int64_t stream_bytes;  // sweeps writing more than this use non-temporal stores
     hipStream_t stream;
 };
+
+// default of Ctx::stream_bytes: half the 256 MB Infinity Cache
+constexpr int64_t kStreamingBytes = int64_t(128) << 20;
 
 // ---- LBM kernels (lbm_kernels.hip) ----
 void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp,

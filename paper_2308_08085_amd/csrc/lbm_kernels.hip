@@ -1197,23 +1197,25 @@ __global__ __launch_bounds__(256) void k_out_gather(DevMesh m, typename Store<S>
 
 // FP64 mass and momentum of the output cells: fixed-order per-block partials,
 // then a single-workgroup fixed-order sum.
+//
+// Body: the partial of the staged blocks with first ID b (256 threads, Mb per
+// block); lane 0 of each block's group returns it in v.
 template <int Q, int S>
-__global__ __launch_bounds__(256) void k_mass_blocks(DevMesh m, typename Store<S>::T *f0, typename Store<S>::T *f1,
-                                                     LevelParams lp, double *part4) {
+__device__ __forceinline__ void mass_block_partial(const DevMesh &m, typename Store<S>::T *f0,
+                                                   typename Store<S>::T *f1, const LevelParams &lp,
+                                                   BlockStage<Lat<Q>, 256 / Lat<Q>::MB> &st, int64_t b, double *v) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     constexpr int MB = Lt::MB, BPW = 256 / MB;
-    __shared__ BlockStage<Lt, BPW> st;
     if ((int)threadIdx.x < BPW) {
-        const int B = blockIdx.x * BPW + threadIdx.x;
-        st.id[threadIdx.x] = (B < m.cap && m.status[B] == ST_UNREF) ? B : -1;
+        const int64_t B = b + threadIdx.x;
+        st.id[threadIdx.x] = (B < m.cap && m.status[B] == ST_UNREF) ? (int)B : -1;
     }
     __syncthreads();
     stage_blocks<Lt, BPW>(m, st);
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
-    const int Braw = blockIdx.x * BPW + s;
     const int B = st.id[s];
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < 4; a++) v[a] = 0.0;
     if (B >= 0 && !((m.gmask[B] >> l) & 1ull)) {
         const int L = m.level[B];
         const typename ST::T *f = lp.par[L] ? f1 : f0;
@@ -1234,8 +1236,18 @@ __global__ __launch_bounds__(256) void k_mass_blocks(DevMesh m, typename Store<S
 #pragma unroll
     for (int off = MB / 2; off > 0; off >>= 1)
         for (int a = 0; a < 4; a++) v[a] += __shfl_xor(v[a], off, 64);
-    if (Braw < m.cap && l == 0)
-        for (int a = 0; a < 4; a++) part4[(int64_t)Braw * 4 + a] = v[a];
+}
+
+template <int Q, int S>
+__global__ __launch_bounds__(256) void k_mass_blocks(DevMesh m, typename Store<S>::T *f0, typename Store<S>::T *f1,
+                                                     LevelParams lp, double *part4) {
+    constexpr int MB = Lat<Q>::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lat<Q>, BPW> st;
+    double v[4];
+    mass_block_partial<Q, S>(m, f0, f1, lp, st, (int64_t)blockIdx.x * BPW, v);
+    const int64_t Braw = (int64_t)blockIdx.x * BPW + threadIdx.x / MB;
+    if (Braw < m.cap && threadIdx.x % MB == 0)
+        for (int a = 0; a < 4; a++) part4[Braw * 4 + a] = v[a];
 }
 
 // Fixed-order sums of the per-block partials: each workgroup reduces one chunk
@@ -1305,11 +1317,9 @@ static inline int grid_blocks(int64_t nblocks, int mb) {
     return (int)((nblocks + bpw - 1) / bpw);
 }
 
-// Output of a level sweep above which its stores bypass the caches: half the
-// 256 MB Infinity Cache.  Smaller levels are still cached when the next sweep
-// (or the interpolation and averaging) reads them.
-constexpr int64_t kStreamingBytes = int64_t(128) << 20;
-
+// A level sweep whose output exceeds c.stream_bytes (by default half the 256 MB
+// Infinity Cache) stores with non-temporal writes.  Smaller levels are still
+// cached when the next sweep (or the interpolation and averaging) reads them.
 template <int Q, int S>
 static void collide_stream_nts(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp,
                                const BCParams &bc) {
@@ -1318,7 +1328,7 @@ static void collide_stream_nts(const Ctx &c, const int32_t *list, int n, int L, 
     const int grid = (n + collide_threads<S>() / c.mb - 1) / (collide_threads<S>() / c.mb);
     const T *src = (const T *)c.f[sp];
     T *dst = (T *)c.f[1 - sp];
-    if ((int64_t)n * Q * c.mb * (int64_t)sizeof(T) > kStreamingBytes)
+    if ((int64_t)n * Q * c.mb * (int64_t)sizeof(T) > c.stream_bytes)
         k_collide_stream<Q, S, true><<<grid, collide_threads<S>(), 0, c.stream>>>(list, n, c.m, src, dst, lp.omega[L], bc);
     else
         k_collide_stream<Q, S, false><<<grid, collide_threads<S>(), 0, c.stream>>>(list, n, c.m, src, dst, lp.omega[L], bc);

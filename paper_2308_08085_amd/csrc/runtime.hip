@@ -343,6 +343,7 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
     c.ctr = (DevCounters *)(a + lay.ctr);
     c.staging = a + lay.staging;
     c.staging_bytes = lay.staging_bytes;
+    c.stream_bytes = kStreamingBytes;
     c.stream = (hipStream_t)hip_stream;
     std::vector<int32_t> slist;
     for (int B = 0; B < (int)h->solid.size(); B++)
@@ -604,6 +605,20 @@ amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf
         if ((*v == 1) != h->force_on) {
             h->force_on = *v == 1;
             drop_graphs(h);  // captured steps hold the exchange launches, or not
+        }
+        return AMR_OK;
+    }
+    if (kind == AMR_FIELD_STREAM_BYTES) {
+        if (!buf || bytes < 8) return fail(AMR_ERR_ARG, "AMR_FIELD_STREAM_BYTES needs an int64 buffer");
+        int64_t *v = (int64_t *)buf;
+        if (op == AMR_GET) {
+            *v = h->c.stream_bytes;
+            return AMR_OK;
+        }
+        if (*v < 0) return fail(AMR_ERR_ARG, "AMR_FIELD_STREAM_BYTES must be >= 0, not %lld", (long long)*v);
+        if (*v != h->c.stream_bytes) {
+            h->c.stream_bytes = *v;
+            drop_graphs(h);  // captured steps hold the store policy of each launch
         }
         return AMR_OK;
     }

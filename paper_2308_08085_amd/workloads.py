@@ -182,6 +182,26 @@ def config4(**kw) -> Case:
     return cylinder(3, 27, (256, 128, 128), 16, 64, 3, 200.0, **args)
 
 
+def config3_reduced(**kw) -> Case:
+    """Set-up 3 at half the root size along each axis: D2Q9 channel 512x128 cells
+    past a 16-cell square cylinder at x = 128, 4 levels, Re 100 (same side
+    ratio, levels, boundaries and schedule)."""
+    args = dict(storage="f32s", seed=2308088, steps=160, adapt_every=32, name="cfg3r_d2q9_cylinder",
+                cap=128 * 32 * 16)
+    args.update(kw)
+    return cylinder(2, 9, (512, 128), 16, 128, 4, 100.0, **args)
+
+
+def config4_reduced(**kw) -> Case:
+    """Set-up 4 at half the root size along each axis: D3Q27 channel 128x64x64
+    cells past an 8-cell square cylinder at x = 32 spanning z, 3 levels, Re 200
+    (same side ratio, levels, boundaries and schedule)."""
+    args = dict(storage="f32s", seed=2308089, steps=128, adapt_every=32, name="cfg4r_d3q27_cylinder",
+                cap=32 * 16 * 16 * 16)
+    args.update(kw)
+    return cylinder(3, 27, (128, 64, 64), 8, 32, 3, 200.0, **args)
+
+
 def config5_cases(n: int = 64, seed: int = 2308090):
     """Batched set-up: n independent cavities, half D2Q9 and half D3Q19, FP16 storage.
 

@@ -1,9 +1,11 @@
-"""The main benchmark set-up at its full size (D3Q27, 256x128x128 root cells,
-near-wall refinement to ~9.3e5 blocks), in the launch configuration the
-benchmark times: sampled cells against the oracle's single-cell collision,
-and properties that hold at any size (a uniform flow is a fixed point of the
-whole step, the tables satisfy the forest invariants, graph replay equals
-eager launches)."""
+"""The main benchmark set-ups at their full size (D3Q27, 256x128x128 root
+cells, near-wall refinement to ~9.3e5 blocks; D2Q9, 1024x256 root cells, 4
+levels), in the launch configuration the benchmark times: sampled blocks of
+every level and boundary class against the oracle run on their patch, the
+synchronisation's interpolation and averaging against the oracle's, and
+properties that hold at any size (a uniform flow is a fixed point of the whole
+step, the tables satisfy the forest invariants, graph replay equals eager
+launches)."""
 import time
 
 import numpy as np
@@ -12,6 +14,7 @@ import pytest
 import oracle
 from paper_2308_08085_amd import abi, workloads as W
 from meshcheck import block_vectors
+from patchcheck import Geometry, block_class, patch, patch_expected
 
 pytestmark = pytest.mark.gpu
 
@@ -130,73 +133,142 @@ def test_graph_replay_equals_eager_at_full_size():
     assert np.array_equal(runs[0], runs[1])
 
 
-def _sampled_level0_check(case, n_blocks=64):
-    """A level-0 leaf whose neighbours are all fluid blocks advances by one
-    collide-stream sweep per coarse step (Secs. "Streaming", "Collision"): the
-    new f_p(x) is population p of the oracle's BGK collision of the pre-step
-    populations at x - c_p.  After near-wall refinement and a few steps, every
-    cell and population of n_blocks such blocks after a graph-replayed coarse
-    step; tolerance: half an ulp of the stored shifted value plus 2e-7."""
+def _tolerance(storage, g_scale, n):
+    """n sweeps, each rounding the stored shifted values (half an ulp: 2^-24
+    relative in FP32, 2^-11 in FP16) plus the FP32 arithmetic (2e-7)"""
+    ulp = 2.0 ** -11 if storage == "f16s" else 2.0 ** -24
+    return n * (ulp * g_scale + 2e-7)
+
+
+def _patch_check(case, g, m, per_class=16):
+    """leaf blocks of every level and class (interior, domain faces, solid
+    neighbours, refined neighbours), one coarse step against the oracle run on
+    the block's patch (patchcheck.py)"""
+    geo = Geometry(case, m)
+    rng = np.random.default_rng(20230808)
+    leaves = np.flatnonzero(m["status"] == 0)
+    rng.shuffle(leaves)
+    picked, counts = [], {}
+    for B in leaves:
+        L = int(m["level"][B])
+        key = (L, block_class(m, B))
+        if counts.get(key, 0) >= per_class:
+            continue
+        p = patch(geo, int(B), 2 ** L)
+        if p is None:
+            continue
+        picked.append((int(B), L, key, p))
+        counts[key] = counts.get(key, 0) + 1
+    need = sorted({N for _, _, _, p in picked for N in p[1].values()})
+    fall = g.get_block_f_all()
+    fpre = {N: fall[N].copy() for N in need}
+    del fall
+    g.step(1, graph=True)
+    fall = g.get_block_f_all()
+    got = {B: fall[B].copy() for B, _, _, _ in picked}
+    del fall
+    _, w, _ = oracle.lattice(case.dim, case.q)
+    worst = {}
+    for B, L, key, p in picked:
+        want = patch_expected(*p, fpre, 2 ** L)
+        g_scale = np.abs(want - w).max(axis=1, keepdims=True)
+        r = (np.abs(got[B] - want) / _tolerance(case.storage, g_scale, 2 ** L)).max()
+        worst[key] = max(worst.get(key, 0.0), float(r))
+    print("  patch check, blocks per (level, class): %s" % sorted(counts.items()), flush=True)
+    print("  max error / tolerance per (level, class): %s" % {k: round(v, 3) for k, v in sorted(worst.items())},
+          flush=True)
+    assert max(worst.values()) <= 1.0, worst
+    return counts
+
+
+def _sync_check(case, g, m, per_level=24):
+    """pre-adaptation synchronisation at full size: ghost cells of sampled
+    children equal the oracle's interpolation of their parent's final cells,
+    and parent cells whose fine cells are not ghosts the oracle's average of
+    the children (Secs. "Linear Interpolation", "Averaging")"""
     d, q = case.dim, case.q
+    mb, nc = (16, 4) if d == 2 else (64, 8)
+    g.tag(tags_in=np.zeros(case.cap, np.int8))  # the synchronisation only
+    n_out = g.n_out()
+    cells = g._fields(abi.AMR_GET, abi.F_CELLS, np.zeros((n_out, 2), np.int32))
+    out = np.zeros((case.cap, mb), bool)
+    out[cells[:, 0], cells[:, 1]] = True
+    del cells
+    f = g.get_block_f_all()
+    ro = oracle.Oracle(W.Case(name="ratios", dim=d, q=q, root=(1, 1, 1), lmax=case.lmax, nu0=case.nu0, cap=1))
+    _, w, _ = oracle.lattice(d, q)
+    geo = Geometry(case, m)
+    rng = np.random.default_rng(7)
+    worst_i = worst_a = 0.0
+    n_i = n_a = 0
+    for L in range(case.lmax - 1):
+        r_cf, r_fc = ro.ratios(L)
+        parents = np.flatnonzero((m["level"] == L) & np.isin(m["status"], (1, 2, 3)))
+        # children with ghost cells (a coarser neighbour) and their parents
+        kids = np.flatnonzero((m["level"] == L + 1) & (m["status"] == 0) & np.any(m["nbr"] == -2, axis=1))
+        for C in rng.choice(kids, min(per_level, len(kids)), replace=False):
+            wc = geo.width(L + 1)
+            xp = [int(v) - int(v) % (2 * wc) for v in m["X"][C]]
+            where = geo.at(L, xp)
+            assert where[0] == "block", (C, where)
+            P = where[1]
+            c = sum(((int(m["X"][C][a]) - xp[a]) // wc) << a for a in range(d))
+            want = oracle.interp_child(d, q, r_cf, f[P], c)
+            ghost = ~out[C]
+            assert ghost.any()
+            gs = np.abs(want[ghost] - w).max(axis=1, keepdims=True)
+            r = (np.abs(f[C][ghost] - want[ghost]) / _tolerance(case.storage, gs, 1)).max()
+            worst_i, n_i = max(worst_i, float(r)), n_i + 1
+        for P in rng.choice(parents, min(per_level, len(parents)), replace=False):
+            first = int(m["nbrc"][P, 0])
+            kids_f = f[first: first + nc]
+            kid_ok = [out[first + c] if m["status"][first + c] == 0 else np.ones(mb, bool) for c in range(nc)]
+            want = oracle.average_parent(d, q, r_fc, kids_f)
+            for l in range(mb):
+                i, j, k = l & 3, (l >> 2) & 3, l >> 4
+                c = (i >> 1) + 2 * (j >> 1) + 4 * (k >> 1)
+                fine = [(2 * (i & 1) + a) + 4 * (2 * (j & 1) + b) + 16 * (2 * (k & 1) + e)
+                        for e in range(2 if d == 3 else 1) for b in range(2) for a in range(2)]
+                if not all(kid_ok[c][x] for x in fine):
+                    continue
+                gs = np.abs(want[l] - w).max()
+                r = (np.abs(f[P][l] - want[l]) / _tolerance(case.storage, gs, 1)).max()
+                worst_a, n_a = max(worst_a, float(r)), n_a + 1
+    del f
+    print("  sync: %d children's ghost cells, %d parent cells; max error / tolerance %.3f (interpolation), "
+          "%.3f (averaging)" % (n_i, n_a, worst_i, worst_a), flush=True)
+    assert n_i > 0 and n_a > 0
+    assert worst_i <= 1.0 and worst_a <= 1.0
+
+
+def _full_size_check(case):
+    """the benchmark's launch configuration (graph replay, non-temporal stores
+    on every level above 128 MiB): one coarse step of sampled leaves against
+    the patch oracle, then the synchronisation's interpolation and averaging"""
     t0 = time.perf_counter()
     g = abi.AmrLbm(case)
     g.set_root_rho_u(case.initial_rho_u())
     refine_near_walls(g, case)
     g.step(6, graph=True)  # a developing flow near the cylinder
     m = g.mesh()
-    nbr = m["nbr"]
-    leaf0 = np.flatnonzero((m["level"] == 0) & (m["status"] == 0))
-    inner = leaf0[np.all(nbr[leaf0] >= 0, axis=1)]
-    assert len(inner) > 4 * n_blocks
-    rng = np.random.default_rng(20230808)
-    # half near the cylinder (more structure), half anywhere
-    X = m["X"].astype(np.int64)
-    # x of the cylinder's first solid block in finest-cell units (4 root cells per block)
-    x_cyl = int(np.flatnonzero(case.solid)[0] % case.root[0]) * 4 * (1 << (case.lmax - 1))
-    near = inner[np.argsort(np.abs(X[inner, 0] - x_cyl))[: 30 * n_blocks]]
-    half = n_blocks // 2
-    sample = np.unique(np.concatenate([rng.choice(near, half, replace=False), rng.choice(inner, half, replace=False)]))
-    vec = np.array(block_vectors(d))
-    c, w, _ = oracle.lattice(d, q)
-    nz = 12 if d == 3 else 1
-    f = g.get_block_f_all()
-    region = np.zeros((len(sample), nz, 12, 12, q))
-    for s_, B in enumerate(sample):
-        for r in range(len(vec)):
-            ox, oy, oz = 4 * (vec[r] + 1)
-            z0, z1 = (oz, oz + 4) if d == 3 else (0, 1)
-            region[s_, z0:z1, oy:oy + 4, ox:ox + 4] = f[nbr[B, r]].reshape((4 if d == 3 else 1), 4, 4, q)
-    del f
-    g.step(1, graph=True)
-    got = g.get_block_f_all()[sample].reshape(len(sample), 4 if d == 3 else 1, 4, 4, q)
-    omega = 1.0 / (3.0 * case.nu0 + 0.5)
-    want = np.zeros_like(got)
-    for s_ in range(len(sample)):
-        post = {}
-        for k in range(4 if d == 3 else 1):
-            for j in range(4):
-                for i in range(4):
-                    for p in range(q):
-                        y = ((4 + k - c[p, 2]) if d == 3 else 0, 4 + j - c[p, 1], 4 + i - c[p, 0])
-                        if y not in post:
-                            post[y] = oracle.collide(d, q, omega, region[(s_,) + y])
-                        want[s_, k, j, i, p] = post[y][p]
-    gshift = np.abs(want - w)
-    tol = (2.0 ** -11 * gshift + 2e-7) if case.storage == "f16s" else (2.0 ** -23 * gshift + 2e-7)
-    err = np.abs(got - want)
-    print("full-size %s %s: %d sampled level-0 blocks, max |f - oracle| %.3e, max err / tol %.3f, %.1f s" %
-          (case.name, case.storage, len(sample), err.max(), (err / tol).max(), time.perf_counter() - t0), flush=True)
-    assert np.all(err <= tol)
+    print("full-size %s %s: blocks per level %s" % (case.name, case.storage, g.counts().tolist()), flush=True)
+    counts = _patch_check(case, g, m)
+    levels = {L for L, _ in counts}
+    assert levels == set(range(case.lmax)), counts
+    assert (case.lmax - 1, "solid") in counts and (case.lmax - 1, "face") in counts and (0, "face") in counts
+    _sync_check(case, g, g.mesh())
+    print("  %.1f s" % (time.perf_counter() - t0), flush=True)
     g.close()
 
 
 @pytest.mark.parametrize("storage", ["f32s", "f16s"])
-def test_sampled_level0_cells_match_the_oracle_at_full_size(storage):
+def test_sampled_blocks_match_the_oracle_at_full_size(storage):
     """the D3Q27 cylinder of the benchmark"""
-    _sampled_level0_check(full_case(storage=storage))
+    _full_size_check(full_case(storage=storage))
 
 
 @pytest.mark.parametrize("storage", ["f32s", "f16s"])
-def test_sampled_level0_cells_match_the_oracle_d2q9_cylinder(storage):
+def test_sampled_blocks_match_the_oracle_d2q9_cylinder(storage):
     """the D2Q9 square cylinder: 1024 x 256 root cells, D = 32, 4 levels"""
-    _sampled_level0_check(W.config3(cap=W.config3().nroot * 12, storage=storage))
+    case = W.config3(cap=W.config3().nroot * 12, storage=storage)
+    _full_size_check(case)

@@ -1,6 +1,7 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the same
-seeded inputs.  Mesh tables bit-exact given identical tags; FP64 fields within
-1e-12 (norm-wise relative), FP32 fields within 1e-5."""
+seeded inputs.  Mesh tables bit-exact given identical tags; fields cell by cell
+(every population of every cell of every active block, rho and u of every
+output cell; parity_util) within 1e-12 for FP64 storage and 1e-5 for FP32."""
 import numpy as np
 import pytest
 
@@ -24,8 +25,7 @@ def test_single_level_fp64(dim, q):
     case = _cav(dim, q, lmax=1)
     p = Pair(case)
     p.step(60)
-    e = p.errors()
-    assert e["f"] < 1e-12 and e["u"] < 1e-12 and e["max_drho"] < 1e-12, e
+    p.assert_parity(1e-12, "single level D%dQ%d" % (dim, q))
     mo, mg = p.o.mass_mom(), p.g.mass_mom()
     assert abs(mo[0] - mg[0]) / mo[0] < 1e-13
 
@@ -56,8 +56,7 @@ def test_random_tags_tables_bitexact(case):
         p.check_mesh("after adapt %d" % it)
         check_forest(case, p.g.mesh())
         p.step(2)
-    e = p.errors()
-    assert e["f"] < 1e-12 and e["u"] < 1e-12, e
+    p.assert_parity(1e-12, case.name)
 
 
 @pytest.mark.parametrize("dim,q", LATTICES)
@@ -74,9 +73,8 @@ def test_amr_cavity_vorticity_fp64(dim, q):
         p.adapt()
         p.check_mesh("cycle %d" % cycle)
     p.step(10)
-    e = p.errors()
     assert len(p.g.mesh()["ids"][2]) > 0
-    assert e["f"] < 1e-12 and e["u"] < 1e-12 and e["max_drho"] < 1e-12, e
+    p.assert_parity(1e-12, "vorticity cavity D%dQ%d" % (dim, q))
 
 
 @pytest.mark.parametrize("dim,q", [(2, 9), (3, 27)])
@@ -95,8 +93,7 @@ def test_cylinder_distance_refinement_fp64(dim, q):
     p.adapt()
     p.check_mesh("vorticity")
     p.step(10)
-    e = p.errors()
-    assert e["f"] < 1e-12 and e["u"] < 1e-12, e
+    p.assert_parity(1e-12, "cylinder D%dQ%d" % (dim, q))
 
 
 @pytest.mark.parametrize("storage,tol", [("f32s", 1e-5), ("f32", 1e-5)])
@@ -110,9 +107,7 @@ def test_fp32_storage_parity(dim, q, storage, tol):
         p.adapt()
         p.check_mesh("cycle %d" % cycle)
     p.step(10)
-    e = p.errors()
-    # f and rho relative to their size; u relative to its own norm
-    assert e["f"] < tol and e["u"] < tol, e
+    p.assert_parity(tol, "%s cavity D%dQ%d" % (storage, dim, q))
 
 
 @pytest.mark.parametrize("storage", ["f16s", "bf16s"])
@@ -125,9 +120,13 @@ def test_half_storage_error_is_bounded(storage):
     p.check_mesh()
     p.step(20)
     e = p.errors()
-    print("%s errors vs FP64 oracle: %s" % (storage, e))
+    print("%s errors vs FP64 oracle: %s" % (storage, e), flush=True)
+    # stated error of the 16-bit storages: norm-wise u, and per cell against
+    # the velocity scale and |f|
     bound = 2e-2 if storage == "f16s" else 1.5e-1
     assert e["u"] < bound and e["f"] < 1e-3, e
+    assert e["u_cell"] < (2e-2 if storage == "f16s" else 2e-1), e
+    assert e["f_cell"] < (5e-3 if storage == "f16s" else 5e-2) and e["block_f_cell"] < (5e-3 if storage == "f16s" else 5e-2), e
 
 
 def test_graph_replay_matches_eager():
@@ -198,9 +197,8 @@ def test_ladder_criterion_fp64(dim, q):
         p.check_mesh("ladder cycle %d" % cycle)
         levels_seen |= {L for L, ids in enumerate(p.g.mesh()["ids"]) if len(ids)}
     p.step(5)
-    e = p.errors()
     assert levels_seen == {0, 1, 2}, levels_seen
-    assert e["f"] < 1e-12 and e["u"] < 1e-12 and e["max_drho"] < 1e-12, e
+    p.assert_parity(1e-12, "ladder D%dQ%d" % (dim, q))
 
 
 @pytest.mark.parametrize("dim,q", LATTICES)
@@ -216,9 +214,8 @@ def test_amr_cavity_cubic_interpolation_fp64(dim, q):
         p.adapt()
         p.check_mesh("cubic cycle %d" % cycle)
     p.step(10)
-    e = p.errors()
     assert len(p.g.mesh()["ids"][2]) > 0
-    assert e["f"] < 1e-12 and e["u"] < 1e-12 and e["max_drho"] < 1e-12, e
+    p.assert_parity(1e-12, "cubic D%dQ%d" % (dim, q))
 
 
 def _force_close(fo, fg, what):
@@ -335,3 +332,65 @@ def test_adaptation_step_times_are_reported():
     st = g.adapt()
     assert st["n_refine"] == 0 and st["step_ms"]["build"] == 0.0 and st["step_ms"]["criterion"] >= 0.0
     g.close()
+
+
+@pytest.mark.parametrize("dim,q,keep", [(2, 9, {(2, 2, 0)}), (3, 19, {(2, 2, 2)}), (3, 27, {(2, 2, 1)})],
+                         ids=["2d_corner", "3d_corner", "3d_edge"])
+def test_edge_and_corner_only_interfaces(dim, q, keep):
+    """every root block but one refined, so that some fine blocks meet the
+    coarse one only at a corner or along an edge (the oracle's classes of these
+    blocks are pinned by hand): the same output cells (ghost masks), tables and
+    fields as the oracle"""
+    case = W.cavity(dim, q, 12, 2, 100.0, cap=64 if dim == 2 else 256, seed=12)
+    p = Pair(case)
+    tags = np.zeros(case.cap, np.int8)
+    r = case.root
+    for k in range(r[2] if dim == 3 else 1):
+        for j in range(r[1]):
+            for i in range(r[0]):
+                if (i, j, k) not in keep:
+                    tags[i + r[0] * (j + r[1] * k)] = 1
+    p.tag_replay(tags)
+    p.adapt()
+    p.check_mesh("edge/corner interfaces")
+    p.step(6)
+    p.assert_parity(1e-12, "edge/corner-only interfaces D%dQ%d" % (dim, q))
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_non_finite_state_is_reported_unstable(graph):
+    """a NaN population set through AMR_FIELD_BLOCK_F: lbm_step with
+    AMR_CHECK_FINITE returns AMR_ERR_UNSTABLE (the FP64 mass sum is not finite)"""
+    case = _cav(3, 19, lmax=2, storage="f32s")
+    g = abi.AmrLbm(case)
+    g.set_root_rho_u(case.initial_rho_u())
+    g.step(2, check_finite=True, graph=graph)
+    f = g.get_block_f_all()
+    B = int(g.mesh()["ids"][0][5])
+    f[B, 21, 3] = np.nan
+    g.set_block_f_all(f)
+    with pytest.raises(abi.AmrError) as e:
+        g.step(1, check_finite=True, graph=graph)
+    assert e.value.code == abi.AMR_ERR_UNSTABLE
+    assert not np.isfinite(g.mass_mom()[0])
+    g.close()
+
+
+def test_stream_bytes_knob():
+    """the store-policy threshold: default 128 MiB, settable to any value >= 0,
+    negative values refused; results are the same with every level streamed"""
+    case = _cav(3, 27, lmax=3, storage="f32s")
+    a, b = abi.AmrLbm(case), abi.AmrLbm(case)
+    assert a.stream_bytes() == 128 << 20
+    assert b.stream_bytes(0) == 0
+    with pytest.raises(abi.AmrError) as e:
+        b.stream_bytes(-1)
+    assert e.value.code == abi.AMR_ERR_ARG and b.stream_bytes() == 0
+    ru = case.initial_rho_u()
+    for g in (a, b):
+        g.set_root_rho_u(ru)
+        g.step(10, graph=True)
+        g.tag(abi.TAG_VORTICITY_REL, theta=0.1)
+        g.adapt()
+        g.step(5, graph=True)
+    assert np.array_equal(a.get_block_f_all(), b.get_block_f_all())

@@ -1,0 +1,72 @@
+"""amr_mass_mom_static, the entry point for callers that cannot allocate: its
+result equals AMR_FIELD_MASS_MOM bit for bit, on two calls in a row with the
+second on a smaller mesh (the shared device array keeps the first call's
+partial sums, which must not leak into the second), and under graph capture."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2308_08085_amd import abi, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(case):
+    g = abi.AmrLbm(case)
+    g.set_root_rho_u(case.initial_rho_u())
+    g.step(6, graph=True)
+    g.tag(abi.TAG_VORTICITY_REL, theta=0.1)
+    g.adapt()
+    g.step(3, graph=True)
+    return g
+
+
+def _static(g):
+    out = torch.full((4,), float("nan"), dtype=torch.float64, device="cuda")
+    g.stream.wait_stream(torch.cuda.current_stream())
+    g.mass_mom_static(out)
+    g.synchronize()
+    return out.cpu().numpy()
+
+
+def test_static_mass_equals_the_arena_form_on_two_calls():
+    big = W.cavity(3, 19, 48, 3, 400.0, storage="f32s", seed=31, cap=12 ** 3 * 24)   # 4 chunks of blocks
+    small = W.cavity(2, 9, 32, 2, 100.0, storage="f64", seed=32)                       # one partial chunk
+    assert big.cap > 4 * 4096 > small.cap
+    for case in (big, small):
+        g = _sim(case)
+        got, want = _static(g), g.mass_mom()
+        print(case.name, case.cap, got, want, flush=True)
+        assert np.array_equal(got, want), (got, want)
+        g.close()
+
+
+def test_static_mass_under_graph_capture():
+    case = W.cavity(3, 27, 16, 2, 100.0, storage="f32s", seed=33)
+    g = _sim(case)
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=g.stream):
+        g.mass_mom_static(out)
+    for _ in range(3):  # replays with eager work and synchronisations between them
+        g.step(2)
+        out.fill_(0.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), g.mass_mom())
+    g.close()
+
+
+def test_static_mass_rejects_meshes_above_its_limit():
+    case = W.cavity(2, 9, 16, 2, 100.0, storage="f16s", cap=4 * 1024 * 4096 + 1)  # an arena of a few GB
+    try:
+        g = abi.AmrLbm(case)
+    except (abi.AmrError, RuntimeError) as e:  # an arena this size may not fit the GPU
+        pytest.skip("arena: %s" % e)
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(abi.AmrError) as e:
+        g.mass_mom_static(out)
+    assert e.value.code == abi.AMR_ERR_CAPACITY
+    g.close()
