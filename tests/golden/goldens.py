@@ -29,13 +29,10 @@ CASES = {
     # the D2Q9 and D3Q27 cylinder set-ups at half the root size, through the
     # frozen near-wall refinement and the vorticity adaptations of their schedule
     "cfg3r_d2q9_cylinder": ("config3_reduced", 1),
+    "cfg4r_d3q27_cylinder": ("config4_reduced", 1),
     # the same without freezing the near-wall refinement, so that the vorticity
     # adaptations coarsen and refine around the cylinder and in the wake
     "cfg3r_d2q9_cylinder_unfrozen": ("config3_reduced", 0),
-}
-# being written: the D3Q27 set-up at half size, frozen and unfrozen
-PENDING = {
-    "cfg4r_d3q27_cylinder": ("config4_reduced", 1),
     "cfg4r_d3q27_cylinder_unfrozen": ("config4_reduced", 0),
 }
 

@@ -128,10 +128,12 @@ def test_schedule_fp32_storage(name):
 
 @pytest.mark.parametrize("name", SCHEDULES)
 def test_schedule_fp64_storage(name):
-    """FP64 storage: sampled cells within 1e-12, mass within 1e-13"""
+    """FP64 storage: sampled cells within 1e-12 (per cell, parity_util), mass and
+    momentum within 1e-12 after every period (FP64 sums of ~1e6 cells in another
+    order differ by ~1e-13)"""
     e = replay(name, "f64", all_streaming=False)
     assert_cells(e, 1e-12, name, e["U"])
-    assert e["mass"] < 1e-13 and e["momentum"] < 1e-12, e
+    assert e["mass"] < 1e-12 and e["momentum"] < 1e-12, e
 
 
 @pytest.mark.parametrize("name", [n for n in SCHEDULES if "unfrozen" not in n])
