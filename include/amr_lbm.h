@@ -266,6 +266,19 @@ amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf
  * synchronised first.  NULL is accepted. */
 amr_status amr_destroy(amr_t *h);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops): the mass and momentum of
+ * AMR_FIELD_MASS_MOM, equal to it bit for bit, written to `out_dev` (4 doubles
+ * of device memory owned by the caller) and only enqueued on the handle's
+ * stream.  It allocates nothing and uses no arena scratch: its partial sums
+ * live in one fixed device array of the library (32 KiB per GPU, held until
+ * the process ends), so meshes of at most 4,194,304 blocks (max_blocks) are
+ * accepted.  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (different streams, or other handles' calls on the same GPU not
+ * ordered with this one) race.
+ * Errors: AMR_ERR_ARG (NULL), AMR_ERR_CAPACITY (max_blocks above the limit),
+ * AMR_ERR_DEVICE. */
+amr_status amr_mass_mom_static(amr_t *h, double *out_dev);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent simulations advanced together.  Not part of the

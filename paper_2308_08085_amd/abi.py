@@ -26,7 +26,8 @@ TAG_VORTICITY_REL, TAG_DISTANCE, TAG_LADDER = 0, 1, 2
 # every symbol the header declares
 EXPORTS = ("amr_query_bytes", "amr_create", "amr_tag", "amr_adapt", "lbm_step", "amr_fields", "amr_destroy",
            "amr_batch_query_bytes", "amr_batch_create", "amr_batch_step", "amr_batch_set_tuning",
-           "amr_batch_get_tuning", "amr_batch_autotune", "amr_batch_destroy", "amr_last_error")
+           "amr_batch_get_tuning", "amr_batch_autotune", "amr_batch_destroy", "amr_mass_mom_static",
+           "amr_last_error")
 
 
 class AmrError(RuntimeError):
@@ -86,6 +87,7 @@ def load():
         L.amr_batch_get_tuning.argtypes = [P, C.POINTER(BatchTuning)]
         L.amr_batch_autotune.argtypes = [P, C.c_int32, C.POINTER(BatchTuning), C.POINTER(C.c_double)]
         L.amr_batch_destroy.argtypes = [P]
+        L.amr_mass_mom_static.argtypes = [P, P]
         L.amr_last_error.restype = C.c_char_p
         for n in EXPORTS[:-1]:
             getattr(L, n).restype = C.c_int32
@@ -248,6 +250,14 @@ class AmrLbm:
         if value is not None:
             self._fields(AMR_SET, F_STREAM_BYTES, np.array([int(value)], np.int64))
         return int(self._fields(AMR_GET, F_STREAM_BYTES, np.zeros(1, np.int64))[0])
+
+    def mass_mom_static(self, out_dev):
+        """amr_mass_mom_static: enqueue the mass/momentum sums into the caller's
+        device buffer `out_dev` (a float64 CUDA tensor of 4 elements)"""
+        import torch
+        assert out_dev.dtype == torch.float64 and out_dev.is_cuda and out_dev.numel() >= 4
+        _check(load().amr_mass_mom_static(self._h, C.c_void_p(out_dev.data_ptr())))
+        return out_dev
 
     def mass_mom(self):
         return self._fields(AMR_GET, F_MASS_MOM, np.zeros(4, np.float64))

@@ -79,6 +79,13 @@ void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const Lev
 void launch_block_f(const Ctx &c, int set, int b0, int b1, double *stage, const LevelParams &lp);
 void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, void *stage, const LevelParams &lp);
 void launch_mass(const Ctx &c, const LevelParams &lp);
+// the same sums through the fixed device array of the library (no arena
+// scratch): its address on `device` (resolved once, with that device
+// current), the largest block capacity it serves, and the launch
+constexpr int kMaxDevices = 64;
+hipError_t mass_scratch(int device, double **ptr);
+int64_t mass_static_max_blocks();
+void launch_mass_static(const Ctx &c, const LevelParams &lp, double *chunks, double *out_dev);
 // momentum exchange with solid blocks: per-level totals out[lmax][3] (device), reset to zero
 void launch_exchange(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp);
 void launch_exchange_batch(hipStream_t stream, int q, int storage, const SimDesc *sims, const uint32_t *items,

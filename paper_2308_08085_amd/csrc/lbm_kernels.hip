@@ -7,6 +7,7 @@
 // Distributions are stored source-indexed in block-major rows (see common.h):
 // every kernel finds population p of a cell with entry_slot().
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -1286,6 +1287,56 @@ __global__ __launch_bounds__(256) void k_mass_final(const double *part4, int cap
     if (threadIdx.x < 4) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
+// The same sums without the arena's per-block partials, for callers that cannot
+// allocate: one workgroup per chunk of kMassChunk blocks forms the block
+// partials itself, BPW blocks at a time, and adds them in the order the
+// per-chunk pass above does (thread t: blocks b0 + t, b0 + t + 256, ...); the
+// chunk sums go to `chunks` (kMassStaticChunks entries at most), and the final
+// pass is the same as above.  The result equals the arena form bit for bit.
+constexpr int kMassStaticChunks = 1024;  // blocks up to 1024 * kMassChunk = 4,194,304
+
+template <int Q, int S>
+__global__ __launch_bounds__(256) void k_mass_chunks_direct(DevMesh m, typename Store<S>::T *f0,
+                                                            typename Store<S>::T *f1, LevelParams lp,
+                                                            double *chunks) {
+    constexpr int MB = Lat<Q>::MB, BPW = 256 / MB;
+    __shared__ BlockStage<Lat<Q>, BPW> st;
+    __shared__ double s_part[256][4];
+    __shared__ double s[4][256];
+    const int64_t b0 = (int64_t)blockIdx.x * kMassChunk;
+    const int t = threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < kMassChunk / 256; r++) {
+        for (int i = 0; i < 256 / BPW; i++) {
+            double v[4];
+            mass_block_partial<Q, S>(m, f0, f1, lp, st, b0 + 256 * r + BPW * i, v);
+            if (t % MB == 0)
+                for (int a = 0; a < 4; a++) s_part[BPW * i + t / MB][a] = v[a];
+            __syncthreads();  // the stage is rewritten by the next group
+        }
+        if (b0 + 256 * r + t < m.cap)
+            for (int a = 0; a < 4; a++) acc[a] += s_part[t][a];
+        __syncthreads();
+    }
+    tree_sum4(s, acc);
+    if (t < 4) chunks[(int64_t)blockIdx.x * 4 + t] = s[t][0];
+}
+
+__global__ __launch_bounds__(256) void k_mass_final_direct(const double *chunks, int cap, double *out) {
+    __shared__ double s[4][256];
+    const int nchunk = (cap + kMassChunk - 1) / kMassChunk;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < nchunk; c += 256)
+        for (int a = 0; a < 4; a++) v[a] += chunks[(int64_t)c * 4 + a];
+    tree_sum4(s, v);
+    if (threadIdx.x < 4) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+// The chunk sums' storage: a fixed array in device memory, one copy per GPU
+// for the life of the process.  Host code uses the address resolved once per
+// device with hipGetSymbolAddress (mass_scratch), never the array's name.
+static __device__ __align__(256) double scratch[kMassStaticChunks * 4];
+
 // ---------------------------------------------------------------------------
 // dispatch over (lattice, storage)
 #define AMR_DISPATCH(qv, sv, BODY)                                                \
@@ -1463,6 +1514,35 @@ void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, voi
     AMR_DISPATCH(c.q, c.storage,
                  (k_out_gather<Qc, Sc><<<grid_blocks(b1 - b0, c.mb), 256, 0, c.stream>>>(
                      c.m, TPTR(Sc, c.f[0]), TPTR(Sc, c.f[1]), lp, kind, b0, b1, c.off, off0, stage)));
+}
+
+int64_t mass_static_max_blocks() { return (int64_t)kMassStaticChunks * kMassChunk; }
+
+hipError_t mass_scratch(int device, double **ptr) {
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {nullptr};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // resolved with its device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (double *)p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
+void launch_mass_static(const Ctx &c, const LevelParams &lp, double *chunks, double *out_dev) {
+    const int nchunk = (c.m.cap + kMassChunk - 1) / kMassChunk;
+    AMR_DISPATCH(c.q, c.storage,
+                 (k_mass_chunks_direct<Qc, Sc><<<nchunk, 256, 0, c.stream>>>(c.m, TPTR(Sc, c.f[0]),
+                                                                            TPTR(Sc, c.f[1]), lp, chunks)));
+    k_mass_final_direct<<<1, 256, 0, c.stream>>>(chunks, c.m.cap, out_dev);
 }
 
 void launch_mass(const Ctx &c, const LevelParams &lp) {

@@ -375,7 +375,12 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
                          });
         for (auto &kv : keyed) root_order.push_back(kv.second);
     }
-    hipError_t e = hipMemcpyAsync(c.order, root_order.data(), root_order.size() * 4, hipMemcpyHostToDevice, c.stream);
+    // the fixed device array of amr_mass_mom_static, resolved once per GPU
+    double *mass_chunks = nullptr;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess) e = mass_scratch(h->device, &mass_chunks);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c.order, root_order.data(), root_order.size() * 4, hipMemcpyHostToDevice, c.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
     if (e == hipSuccess && !h->solid.empty()) {
         e = hipMemcpyAsync(c.solid, h->solid.data(), h->solid.size(), hipMemcpyHostToDevice, c.stream);
@@ -583,6 +588,19 @@ amr_status amr_adapt(amr_t *h, amr_adapt_stats *stats) {
         for (int L = 0; L < h->lmax; L++) stats->level_blocks[L] = h->nids[L];
         for (int k = 0; k < AMR_T_STEPS; k++) stats->step_ms[k] = h->step_ms[k];
     }
+    return AMR_OK;
+}
+
+amr_status amr_mass_mom_static(amr_t *h, double *out_dev) {
+    if (!h) return fail(AMR_ERR_ARG, "handle is NULL");
+    if (!out_dev) return fail(AMR_ERR_ARG, "out_dev is NULL");
+    if ((int64_t)h->c.m.cap > mass_static_max_blocks())
+        return fail(AMR_ERR_CAPACITY, "amr_mass_mom_static serves meshes of at most %lld blocks, this one has %d",
+                    (long long)mass_static_max_blocks(), h->c.m.cap);
+    double *chunks = nullptr;
+    HIP_TRY(mass_scratch(h->device, &chunks));
+    launch_mass_static(h->c, level_params(h), chunks, out_dev);
+    HIP_TRY(hipGetLastError());
     return AMR_OK;
 }
 

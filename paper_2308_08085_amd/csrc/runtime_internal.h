@@ -37,6 +37,7 @@ struct amr_handle {
     Ctx c;
     Layout lay;
     int lmax;
+    int device;  // the GPU current at creation
     int nids[kMaxLevels], niface[kMaxLevels], nsolid[kMaxLevels];
     int gtop;
     int par[kMaxLevels];
