@@ -35,23 +35,48 @@ if HERE not in sys.path:
 
 METRIC = "AMR-LBM MLUPS (FP32 vs FP16-storage) + adapt ms/cycle; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the dominant kernel on the main workload, from two
-# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, per
-# dispatch), each scaled by what the counter reads for a 1 GiB copy
-# (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Must be measured
-# again whenever the kernel changes.
-MEASURED_TRAFFIC = {"k_collide_stream<27, F32S>": (1857239.49 * 2.0 + 3050592.42 * 1.0) * 1024,
-                    "k_collide_stream<27, F16S>": (922192.99 * 2.0 + 1531613.87 * 1.0) * 1024,
-                    # the uniform 384^3 sweep (its levels are written with non-temporal stores,
-                    # unlike the cavity's, which run the other instantiation of the kernel)
-                    "k_collide_stream<19, F32S, uniform 384^3>": (2500281.60 * 2.0 + 4202496.02 * 1.0) * 1024}
+# HBM bytes per launch of a kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE, per dispatch), each scaled by what the counter reads for a
+# copy of known size: the committed summaries under profiles/ carry one
+# "TRAFFIC_JSON {...}" line per kernel and workload, with the hash of the
+# kernel sources the counters were taken on.  A summary taken on other sources
+# gives no traffic figure (null).
+KERNEL_SOURCES = ("paper_2308_08085_amd/csrc/lbm_kernels.hip", "paper_2308_08085_amd/csrc/common.h")
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """{key: bytes per launch} from profiles/*.md, for the current kernel sources"""
+    out, cur = {}, source_hash()
+    pdir = os.path.join(HERE, "profiles")
+    for name in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as fh:
+            for ln in fh:
+                if ln.startswith("TRAFFIC_JSON "):
+                    d = json.loads(ln[len("TRAFFIC_JSON "):])
+                    if d.get("source_sha") == cur:
+                        out[d["key"]] = (d["fetch_kib"] * d["fetch_scale"] + d["write_kib"] * d["write_scale"]) * 1024
+    return out
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=True, tag_kind=None):
+def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=True, tag_kind=None,
+                keep_state=False):
+    """keep_state: also return the tags of every adaptation and the final rho/u
+    of the output cells (for the error leg)"""
     import torch
     from paper_2308_08085_amd import abi, workloads as W
 
@@ -65,6 +90,7 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
     ev1 = torch.cuda.Event(enable_timing=True)
     refused = [0]
     steps_ms = {k: 0.0 for k in abi.ADAPT_STEPS}  # device time per adaptation step, summed
+    tags_seq = []
 
     def one_period(profile=False, check=False):
         counts = g.counts().copy()
@@ -74,9 +100,11 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
         g.synchronize()  # the adaptation clock starts once the advancement has finished
         t0 = time.perf_counter()
         if tag_kind == abi.TAG_LADDER:
-            g.tag(abi.TAG_LADDER, n_start=-2.0, n_inc=1.0)
+            tg = g.tag(abi.TAG_LADDER, n_start=-2.0, n_inc=1.0)
         else:
-            g.tag(abi.TAG_VORTICITY_REL, theta=theta)
+            tg = g.tag(abi.TAG_VORTICITY_REL, theta=theta)
+        if keep_state:
+            tags_seq.append(tg)
         try:
             st = g.adapt()
             for k, v in st["step_ms"].items():
@@ -124,6 +152,9 @@ def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=Tr
         "kernels": {k: {"launches": int(v[0]), "ms": v[1], "blocks": v[2], "bytes": v[3]} for k, v in ks.items()},
         "adaptations_refused_for_capacity": refused[0],
     }
+    if keep_state:
+        out["tags_seq"] = tags_seq
+        out["rho_u"] = g.rho_u_out()
     g.close()
     del g
     torch.cuda.empty_cache()
@@ -278,6 +309,7 @@ def copy_bandwidth(gib=1, reps=10):
 
 
 COPY_GBS = [None]  # measured once per run
+TRAFFIC = {}  # measured_traffic(), read once per run
 
 
 def uniform_sweep(steps=20):
@@ -311,7 +343,7 @@ def uniform_sweep(steps=20):
 def roofline(res, kernel):
     k = res["kernels"]["collide_stream"]
     gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9
-    traffic = MEASURED_TRAFFIC.get(kernel)
+    traffic = TRAFFIC.get(kernel)
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic) if traffic else None,
             "copy_GBs": round(COPY_GBS[0], 1) if COPY_GBS[0] else None,
@@ -320,6 +352,42 @@ def roofline(res, kernel):
             "kernel": kernel,
             "avg_launch_us": round(k["ms"] * 1e3 / max(k["launches"], 1), 2),
             "bytes_per_launch": round(k["bytes"] / max(k["launches"], 1))}
+
+
+def replay_error(case, res, storage_ref="f64"):
+    """velocity error of a run (res from run_storage with keep_state) against
+    the same schedule with FP64 storage and the same tags (the FP64 storage is
+    held to the FP64 oracle within 1e-12 by the parity tests)"""
+    from paper_2308_08085_amd import abi
+
+    t0 = time.perf_counter()
+    g = abi.AmrLbm(case, storage=storage_ref)
+    g.set_root_rho_u(case.initial_rho_u())
+    for _ in range(case.dist_levels):
+        g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=1)
+        g.adapt()
+    for t in res["tags_seq"]:
+        g.step(case.adapt_every, graph=True)
+        g.tag(tags_in=t)
+        try:
+            g.adapt()
+        except abi.AmrError as e:
+            if e.code != abi.AMR_ERR_CAPACITY:
+                raise
+    ref = g.rho_u_out()
+    g.close()
+    got = res["rho_u"]
+    if ref.shape != got.shape:
+        return {"error": "output cells differ"}
+    U = float(np.abs(np.asarray(case.face_u)).max())
+    du = got[:, 1:4] - ref[:, 1:4]
+    out = {"u_l2_rel": float(np.linalg.norm(du) / np.linalg.norm(ref[:, 1:4])),
+           "u_max_abs_over_U": float(np.abs(du).max() / U),
+           "rho_max_abs": float(np.abs(got[:, 0] - ref[:, 0]).max()),
+           "coarse_steps": len(res["tags_seq"]) * case.adapt_every, "reference": "FP64 storage, same tags",
+           "seconds": round(time.perf_counter() - t0, 1)}
+    log("[error] %s" % out)
+    return out
 
 
 def error_leg(theta):
@@ -358,45 +426,58 @@ def error_leg(theta):
     return out
 
 
-def cpu_baseline(theta, seconds=20.0):
-    """the FP64 oracle on a bounded sample of the same workload, one host thread"""
+def cpu_baseline(case):
+    """The FP64 oracle on the main workload's own mesh (the same near-wall
+    refinement at t = 0 as the GPU run, so the same 9.3e5 blocks), on the
+    host cores: one collide-stream sweep of levels 0 and 1 on one thread
+    pinned to one core, then one whole coarse step on every core the process
+    may use"""
     import oracle
-    from paper_2308_08085_amd import workloads as W
 
-    case = W.config4()
+    cores = sorted(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    oracle.set_threads(len(cores))
     o = oracle.Oracle(case)
     o.set_root_rho_u(case.initial_rho_u())
-    tot_u = tot_s = 0.0
-    n = 0
-    adapt_s = None
-
-    def counts():
-        return [len(x) for x in o.mesh()["ids"]]
-
-    t_begin = time.perf_counter()
-    while time.perf_counter() - t_begin < seconds:
-        c = counts()
-        t0 = time.perf_counter()
-        o.step(1)
-        dt = time.perf_counter() - t0
-        tot_u += W.mlups_updates(c, case.dim)
-        tot_s += dt
-        n += 1
-        if n == 2 and adapt_s is None:
-            t0 = time.perf_counter()
-            o.tag(kind=0, theta=theta)
-            o.adapt()
-            adapt_s = time.perf_counter() - t0
+    for _ in range(case.dist_levels):
+        o.tag(kind=1, d_spec=case.d_spec, freeze=1)
+        o.adapt()
+    counts = [len(x) for x in o.mesh()["ids"]]
+    setup_s = time.perf_counter() - t0
+    log("[cpu] oracle set up on the main mesh %s in %.1f s" % (counts, setup_s))
+    # one thread on one core: the level-0 and level-1 sweeps
+    os.sched_setaffinity(0, {cores[0]})
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    o.sweep(0)
+    o.sweep(1)
+    one_s = time.perf_counter() - t0
+    os.sched_setaffinity(0, set(cores))
+    one_cells = (counts[0] + counts[1]) * case.mb
+    log("[cpu] one core: %d cell updates in %.1f s" % (one_cells, one_s))
+    # every core: a whole coarse step (every level, interpolation, averaging)
+    n = oracle.set_threads(len(cores))
+    from paper_2308_08085_amd import workloads as W
+    t0 = time.perf_counter()
+    o.step(1)
+    all_s = time.perf_counter() - t0
+    upd = W.mlups_updates(counts, case.dim)
+    log("[cpu] %d threads: one coarse step (%.0f M updates) in %.1f s" % (n, upd / 1e6, all_s))
+    del o
     model = None
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": round(tot_u / tot_s / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle", "cpu": model,
-            "adapt_ms_per_cycle": round(adapt_s * 1e3, 1) if adapt_s else None,
-            "sample": "same cylinder set-up, FP64 oracle, one thread: %d coarse steps from the initial field "
-                      "with one vorticity adaptation after step 2 (%.1f s of stepping)" % (n, tot_s)}
+    return {"value": round(upd / all_s / 1e6, 2), "unit": "MLUPS", "cores": n, "kind": "oracle", "cpu": model,
+            "sample": "FP64 oracle on the main workload's mesh after its near-wall refinement (blocks per level %s): "
+                      "one coarse step (all levels, interpolation, averaging) on %d threads, %.1f s; MLUPS by the "
+                      "paper's leaf-weighted count" % (counts, n, all_s),
+            "one_core": {"value": round(one_cells / one_s / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                         "sample": "one collide-stream sweep each of levels 0 and 1 (%d cell updates), one thread "
+                                   "pinned to one core, %.1f s" % (one_cells, one_s)},
+            "setup_s": round(setup_s, 1)}
 
 
 def main():
@@ -410,6 +491,7 @@ def main():
     ap.add_argument("--no-cavity", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-uniform", action="store_true")
+    ap.add_argument("--no-d2q9", action="store_true", help="skip the D2Q9 cavity and cylinder legs")
     ap.add_argument("--no-extensions", action="store_true")
     ap.add_argument("--physics", action="store_true",
                     help="only the paper's square-cylinder runs: C_D and St against its table")
@@ -457,13 +539,29 @@ def main():
 
     abi.load()
     log("device:", torch.cuda.get_device_name(0))
+    TRAFFIC.update(measured_traffic())
     COPY_GBS[0] = copy_bandwidth()
     log("[copy] 1 GiB device-to-device: %.1f GB/s" % COPY_GBS[0])
     main_case = W.config4(cap=W.config4().nroot * 16)
     cav = W.config2()
     theta = main_case.theta
-    r32 = run_storage(main_case, "f32s", args.steps, args.warmup, theta)
-    r16 = None if args.no_fp16 else run_storage(main_case, "f16s", args.steps, args.warmup, theta)
+    keep = not args.no_error_leg
+    r32 = run_storage(main_case, "f32s", args.steps, args.warmup, theta, keep_state=keep)
+    e32 = replay_error(main_case, r32) if keep else None
+    r16 = None if args.no_fp16 else run_storage(main_case, "f16s", args.steps, args.warmup, theta, keep_state=keep)
+    e16 = replay_error(main_case, r16) if (keep and r16 is not None) else None
+    for r in (r32, r16):
+        if r is not None:
+            r.pop("rho_u", None)
+            r.pop("tags_seq", None)
+    d2 = None
+    if not args.no_d2q9:
+        # set-up 1 (D2Q9 FP64 cavity) and set-up 3 (D2Q9 cylinder, FP32 against FP16)
+        c1 = W.config1()
+        c3 = W.config3(cap=W.config3().nroot * 12)
+        d2 = {"cfg1": run_storage(c1, "f64", max(2, args.steps // 2), 2, theta),
+              "cfg3_f32s": run_storage(c3, "f32s", args.steps, args.warmup, theta),
+              "cfg3_f16s": None if args.no_fp16 else run_storage(c3, "f16s", args.steps, args.warmup, theta)}
     c32 = None if args.no_cavity else run_storage(cav, "f32s", args.steps, args.warmup, theta)
     c16 = None if (args.no_cavity or args.no_fp16) else run_storage(cav, "f16s", args.steps, args.warmup, theta)
     ext = None
@@ -483,7 +581,7 @@ def main():
         log("[uniform] %s: %.1f MLUPS, collide %.1f GB/s" % (uni["workload"], uni["mlups"], uni["roofline"]["achieved"]))
     bat = None if args.no_batch else run_batch(max(2, args.steps // 2), 2, theta)
     err = None if args.no_error_leg else error_leg(theta)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(theta)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(main_case)
     line = {
         "metric": METRIC,
         "value": round(r32["mlups"], 1),
@@ -509,6 +607,7 @@ def main():
         "mlups_incl_adapt": round(r32["mlups_wall"], 1),
         "roofline": roofline(r32, "k_collide_stream<27, F32S>"),
         "kernels_f32s": kernel_rates(r32),
+        "error_f32s_vs_fp64_storage": e32,
         "cpu_baseline": cpu,
     }
     if r16 is not None:
@@ -516,6 +615,7 @@ def main():
                          "speedup_vs_fp32": round(r16["mlups"] / r32["mlups"], 3),
                          "roofline": roofline(r16, "k_collide_stream<27, F16S>"),
                          "kernels": kernel_rates(r16),
+                         "error_vs_fp64_storage": e16,
                          "level_blocks_end": r16["level_blocks"]}
     if c32 is not None:
         line["cavity_d3q19"] = {
@@ -525,6 +625,24 @@ def main():
         if c16 is not None:
             line["cavity_d3q19"]["mlups_f16s"] = round(c16["mlups"], 1)
             line["cavity_d3q19"]["speedup_f16s_vs_f32s"] = round(c16["mlups"] / c32["mlups"], 3)
+    if d2 is not None:
+        r1, a3, b3 = d2["cfg1"], d2["cfg3_f32s"], d2["cfg3_f16s"]
+        line["cavity_d2q9_fp64"] = {
+            "workload": "D2Q9 lid-driven cavity, 64^2 root cells, 3 levels, Re 100, FP64, adapt every 100",
+            "mlups": round(r1["mlups"], 1), "adapt_ms_per_cycle": round(r1["adapt_ms_per_cycle"], 3),
+            "roofline": roofline(r1, "k_collide_stream<9, F64>"), "kernels": kernel_rates(r1),
+            "level_blocks_end": r1["level_blocks"]}
+        line["cylinder_d2q9"] = {
+            "workload": "D2Q9 flow past a square cylinder, 1024x256 root cells, side 32 at x = 256, Re 100, "
+                        "4 levels, near-wall refinement at t = 0 + vorticity tagging every 32 coarse steps",
+            "mlups_f32s": round(a3["mlups"], 1), "adapt_ms_per_cycle_f32s": round(a3["adapt_ms_per_cycle"], 3),
+            "roofline_f32s": roofline(a3, "k_collide_stream<9, F32S>"), "kernels_f32s": kernel_rates(a3),
+            "level_blocks_end": a3["level_blocks"]}
+        if b3 is not None:
+            line["cylinder_d2q9"].update({
+                "mlups_f16s": round(b3["mlups"], 1), "adapt_ms_per_cycle_f16s": round(b3["adapt_ms_per_cycle"], 3),
+                "speedup_f16s_vs_f32s": round(b3["mlups"] / a3["mlups"], 3),
+                "roofline_f16s": roofline(b3, "k_collide_stream<9, F16S>"), "kernels_f16s": kernel_rates(b3)})
     if ext is not None:
         line["extensions"] = ext
     if uni is not None:

@@ -67,7 +67,7 @@ def lib():
                      "orc_lattice", "orc_feq", "orc_collide", "orc_interp_child", "orc_interp_child_cubic",
                      "orc_average_parent",
                      "orc_parity", "orc_force", "orc_get_f_all", "orc_cell_classes", "orc_set_threads",
-                     "orc_ratios"):
+                     "orc_ratios", "orc_sweep"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -165,8 +165,8 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().orc_destroy(C.c_void_p(h))
+        if h and _lib is not None:
+            _lib.orc_destroy(C.c_void_p(h))
             self._h = None
 
     @property
@@ -201,6 +201,12 @@ class Oracle:
 
     def step(self, n: int = 1):
         lib().orc_step(self.h, int(n))
+
+    def sweep(self, L: int):
+        """one collide-stream sweep of level L alone (timing only: the forest is
+        left mid-step)"""
+        if lib().orc_sweep(self.h, int(L)) != 0:
+            raise ValueError("no level %d" % L)
 
     def sync(self):
         lib().orc_sync(self.h)

@@ -749,6 +749,15 @@ static void step_level(orc_t *o, int L)
     average_level(o, L, 0);
 }
 
+/* one collide-and-stream sweep of level L alone (timing of the CPU
+ * baseline): the level's buffer advances, the forest is left mid-step */
+int orc_sweep(orc_t *o, int32_t L)
+{
+    if (L < 0 || L >= o->lmax) return -1;
+    collide_stream_level(o, L);
+    return 0;
+}
+
 int orc_step(orc_t *o, int32_t n)
 {
     for (int32_t s = 0; s < n; s++) step_level(o, 0);
@@ -1068,6 +1077,7 @@ int orc_adapt(orc_t *o, int32_t *stats)
 
     /* S7: interpolate to the new children from their parents' data, then
      * finalise statuses and branch/leaf */
+#pragma omp parallel for schedule(dynamic, 4)
     for (int32_t P = 0; P < o->cap; P++)
         if (first[P] >= 0) interp_parent(o, o->level[P], P, 1);
     for (int32_t B = 0; B < o->cap; B++) {

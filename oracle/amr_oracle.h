@@ -79,6 +79,8 @@ int orc_cell_classes(orc_t *o, int32_t B, int32_t *out);
 /* host threads of the per-block loops (n <= 0: unchanged); returns the count in use */
 int orc_set_threads(int n);
 int orc_step(orc_t *o, int32_t n_coarse_steps);
+/* one collide-stream sweep of level L alone (for timing; leaves the forest mid-step) */
+int orc_sweep(orc_t *o, int32_t L);
 int orc_sync(orc_t *o);
 int orc_tag(orc_t *o, const orc_tag_params *p, const int8_t *tags_in, int8_t *tags_out);
 int orc_adapt(orc_t *o, int32_t *stats /* [4]: n_refine, n_coarsen, n_reverted, n_ignored */);

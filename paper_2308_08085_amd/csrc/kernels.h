@@ -19,6 +19,11 @@ struct DevCounters {
     int32_t totals[kMaxLevels];
     int32_t bases[kMaxLevels];
     double mass[4];
+    // cells the solver's grid communication moves from level L, per coarse
+    // step of L: ghost cells its interpolation writes into level L+1, parent
+    // cells its averaging writes (each from 2^d fine cells)
+    unsigned long long ghost_w[kMaxLevels];
+    unsigned long long avg_w[kMaxLevels];
 };
 
 // everything a launcher needs: device views and scratch carved from the arena

@@ -760,6 +760,46 @@ __global__ void k_solid_lists(const DevMesh m, const int8_t *bins, const int32_t
         for (int L = 0; L < kMaxLevels; L++) ctr->nsolid[L] = L < m.lmax ? ctr->totals[L] : 0;
 }
 
+// Cells the interpolation and the averaging of each level move (for the
+// byte counts of the solver's kernel statistics): over the interface parents
+// of level L, the ghost cells of their children and the parent cells whose
+// first fine cell (even i, j, k) is an interface cell.
+__global__ void k_target_reset(DevCounters *ctr) {
+    if (threadIdx.x < kMaxLevels) {
+        ctr->ghost_w[threadIdx.x] = 0;
+        ctr->avg_w[threadIdx.x] = 0;
+    }
+}
+
+// One thread per interface parent of one level (grid y = level); the sums
+// are reduced over the wave before one atomic per wave.
+template <typename Dd>
+__global__ __launch_bounds__(256) void k_target_cells(DevMesh m, const int32_t *__restrict__ iface,
+                                                      DevCounters *ctr) {
+    const int L = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long g = 0, a = 0;
+    if (i < ctr->niface[L]) {
+        const int P = iface[(int64_t)L * m.cap + i];
+        const int first = m.nbrc[P];
+        // fine cells with even coordinates: the first of each parent cell's 2^d
+        const uint64_t lead = Dd::D == 3 ? 0x0000050500000505ull : 0x0505ull;
+        if (first >= 0 && first <= m.cap - Dd::NC)
+            for (int c = 0; c < Dd::NC; c++) {
+                g += __popcll(m.gmask[first + c]);
+                a += __popcll(m.imask[first + c] & lead);
+            }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        g += __shfl_xor(g, off, 64);
+        a += __shfl_xor(a, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (g) atomicAdd(&ctr->ghost_w[L], g);
+        if (a) atomicAdd(&ctr->avg_w[L], a);
+    }
+}
+
 template <typename Dd>
 void masks_and_lists(const Ctx &c) {
     const int cap = c.m.cap;
@@ -777,6 +817,8 @@ void masks_and_lists(const Ctx &c) {
     run_scan(c, c.bins, cap, c.m.lmax);
     k_solid_lists<<<grid_for(cap), 256, 0, c.stream>>>(c.m, c.bins, c.rank, c.solidl, c.ctr);
     build_order<Dd>(c);
+    k_target_reset<<<1, 64, 0, c.stream>>>(c.ctr);
+    k_target_cells<Dd><<<dim3(grid_for(cap), c.m.lmax), 256, 0, c.stream>>>(c.m, c.iface, c.ctr);
 }
 
 template <typename Dd>

@@ -140,19 +140,20 @@ hipEvent_t take_event(amr_handle *h) {
 }
 
 // distribution bytes a launch must move: every cell of a processed block reads
-// and writes Q populations (collide-stream); a ghost fill reads the parent and
-// writes its children's ghost cells; an average reads 2^d fine cells per parent
-// cell and writes it.  Counted per block at the upper bound of the targets.
-double launch_bytes(const amr_handle *h, int kind, double blocks) {
+// and writes Q populations (collide-stream, plus the block's links, flags and
+// list entry); a ghost fill of level L reads each interface parent's cells and
+// writes the ghost cells of its children; an average writes each targeted
+// parent cell from 2^d fine cells (both plus the children's cell masks).
+double launch_bytes(const amr_handle *h, int kind, double blocks, int L) {
     const double q = h->c.q, mb = h->c.mb, nc = h->c.nc, sb = (double)storage_bytes(h->c.storage);
     const double links = h->c.nb * 4.0 + 1.0 + 4.0;
     if (kind == 0) return blocks * (2.0 * q * mb * sb + links);
-    if (kind == 1) return blocks * (q * mb * sb + nc * q * mb * sb + 8.0 * nc);
-    return blocks * (nc * q * mb * sb + q * mb * sb + 8.0 * nc);
+    if (kind == 1) return blocks * (q * mb * sb + 8.0 * nc) + h->ghost_w[L] * q * sb;
+    return blocks * 8.0 * nc + h->avg_w[L] * (nc + 1.0) * q * sb;
 }
 
 template <typename F>
-void timed_launch(amr_handle *h, int kind, int blocks, F &&fn) {
+void timed_launch(amr_handle *h, int kind, int blocks, int L, F &&fn) {
     if (!h->profiling || blocks <= 0) {
         fn();
         return;
@@ -161,12 +162,12 @@ void timed_launch(amr_handle *h, int kind, int blocks, F &&fn) {
     if (a) hipEventRecord(a, h->c.stream);
     fn();
     if (b) hipEventRecord(b, h->c.stream);
-    if (a && b) h->timed.push_back({kind, a, b, (double)blocks, launch_bytes(h, kind, blocks)});
+    if (a && b) h->timed.push_back({kind, a, b, (double)blocks, launch_bytes(h, kind, blocks, L)});
 }
 
 void collide_stream(amr_handle *h, int L) {
     const LevelParams lp = level_params(h);
-    timed_launch(h, 0, h->nids[L], [&] {
+    timed_launch(h, 0, h->nids[L], L, [&] {
         launch_collide_stream(h->c, h->c.order + (size_t)L * h->c.m.cap, h->nids[L], L, lp, h->bc);
     });
     h->par[L] ^= 1;
@@ -184,14 +185,14 @@ void step_level(amr_handle *h, int L) {
     const size_t cap = (size_t)h->c.m.cap;
     if (h->niface[L] > 0) {
         const LevelParams lp = level_params(h);
-        timed_launch(h, 1, h->niface[L], [&] { launch_interp(h->c, h->c.iface + L * cap, h->niface[L], lp, 0); });
+        timed_launch(h, 1, h->niface[L], L, [&] { launch_interp(h->c, h->c.iface + L * cap, h->niface[L], lp, 0); });
     }
     collide_stream(h, L);
     step_level(h, L + 1);
     step_level(h, L + 1);
     if (h->niface[L] > 0) {
         const LevelParams lp = level_params(h);
-        timed_launch(h, 2, h->niface[L], [&] { launch_average(h->c, h->c.iface + L * cap, h->niface[L], lp, 0); });
+        timed_launch(h, 2, h->niface[L], L, [&] { launch_average(h->c, h->c.iface + L * cap, h->niface[L], lp, 0); });
     }
 }
 
@@ -225,6 +226,8 @@ amr_status refresh_counts(amr_handle *h) {
         h->nids[L] = L < h->lmax ? dc.nids[L] : 0;
         h->niface[L] = L < h->lmax ? dc.niface[L] : 0;
         h->nsolid[L] = L < h->lmax ? dc.nsolid[L] : 0;
+        h->ghost_w[L] = L < h->lmax ? (double)dc.ghost_w[L] : 0.0;
+        h->avg_w[L] = L < h->lmax ? (double)dc.avg_w[L] : 0.0;
     }
     h->gtop = dc.gtop;
     return AMR_OK;

@@ -39,6 +39,7 @@ struct amr_handle {
     int lmax;
     int device;  // the GPU current at creation
     int nids[kMaxLevels], niface[kMaxLevels], nsolid[kMaxLevels];
+    double ghost_w[kMaxLevels], avg_w[kMaxLevels];  // cells the grid communication of each level moves
     int gtop;
     int par[kMaxLevels];
     double force_sweeps[kMaxLevels] = {0};  // collide-stream sweeps per level since the force reset
@@ -66,5 +67,6 @@ namespace amr {
 
 // relaxation and rescaling of every level, with the current buffer parities
 LevelParams level_params(const amr_handle *h);
+
 
 }  // namespace amr
