@@ -121,51 +121,70 @@ __device__ __forceinline__ void scatter_cell(const DevMesh &m, const int32_t *li
     for (int p = 0; p < Lt::Q; p++) store_g<Lt, ST>(f, entry_slot<Lt>(m, link, B, h, p, l), p, g[p]);
 }
 
-// Source block of population p (velocity c) for a cell of an interior 3-D
-// block, from the wave-uniform region links nb[27]: wx/wy/wz say whether the
-// source cell x - c lies across the block face along that axis.
-template <int CX, int CY, int CZ>
-__device__ __forceinline__ int32_t pick_src(const int32_t *nb, bool wx, bool wy, bool wz) {
-    // plain values first: a conditional over two array elements would be an
-    // lvalue and turn into a runtime index into the array
-    const int32_t n000 = nb[offset_slot(0, 0, 0)], n100 = nb[offset_slot(-CX, 0, 0)];
-    const int32_t n010 = nb[offset_slot(0, -CY, 0)], n110 = nb[offset_slot(-CX, -CY, 0)];
-    const int32_t n001 = nb[offset_slot(0, 0, -CZ)], n101 = nb[offset_slot(-CX, 0, -CZ)];
-    const int32_t n011 = nb[offset_slot(0, -CY, -CZ)], n111 = nb[offset_slot(-CX, -CY, -CZ)];
-    const int32_t a = wx ? n100 : n000, b = wx ? n110 : n010;
-    const int32_t c = wx ? n101 : n001, d = wx ? n111 : n011;
-    const int32_t z0 = wy ? b : a, z1 = wy ? d : c;
-    return wz ? z1 : z0;
-}
+// Gather of an interior 3-D block (every region link a same-level block; one
+// block per wave) through a per-wave LDS table of its 27 region rows.
+//
+// Population p of cell (i, j, k) comes from cell s = (i, j, k) - c_p, which
+// lies in region r = floor(s / 4) (per axis -1, 0 or +1) at local cell s - 4 r.
+// Its address is row(r) + p Mb + (s - 4 r) . (1, 4, 16), i.e.
+//     tab[r] + own + (p Mb - c_p . (1, 4, 16))   (in elements)
+// with tab[r] = row(r) - 4 r . (1, 4, 16) stored per region, own = the
+// lane's cell index, and the last term a constant of p.  The region offset
+// along x is -1 only for c_x = +1 on the face i = 0 and +1 only for c_x = -1 on
+// i = 3, so each lane keeps one table offset per axis and sign of c.  Per
+// population that is one three-way add for the table entry, one LDS read and
+// one 64-bit add, with no selects and no 64-bit multiplies.
+struct InteriorLane {
+    uint32_t xm, x0, xp;  // LDS byte address of tab[13 + r_x] for c_x = -1 / 0 / +1
+    uint32_t ym, yp;      // byte offset of the y part of the region for c_y = -1 / +1
+    uint32_t zm, zp;      // the same along z
+    uint32_t own;         // byte offset of the lane's own cell in a row
+};
 
-template <typename Lt, int P>
-__device__ __forceinline__ int64_t interior_slot(const int32_t *nb, int i, int j, int k) {
-    constexpr int cx = Lt::cx(P), cy = Lt::cy(P), cz = Lt::cz(P);
-    const bool wx = (cx > 0 && i == 0) || (cx < 0 && i == 3);
-    const bool wy = (cy > 0 && j == 0) || (cy < 0 && j == 3);
-    const bool wz = (cz > 0 && k == 0) || (cz < 0 && k == 3);
-    const int32_t id = pick_src<cx, cy, cz>(nb, wx, wy, wz);
-    const int ls = ((i - cx) & 3) + 4 * ((j - cy) & 3) + 16 * ((k - cz) & 3);
-    return (int64_t)id * (Lt::Q * Lt::MB) + (P * Lt::MB + ls);
-}
-
-// wave-uniform copies of the 27 region links (constant indices throughout, so
-// the array lives in scalar registers)
-template <int R>
-__device__ __forceinline__ void uniform_links(const int32_t *link, int32_t *nb) {
-    if constexpr (R < 27) {
-        nb[R] = __builtin_amdgcn_readfirstlane(link[R]);
-        uniform_links<R + 1>(link, nb);
-    }
+template <typename T>
+__device__ __forceinline__ InteriorLane interior_lane(const uint64_t *tab, int i, int j, int k) {
+    InteriorLane u;
+    // LDS byte offset of the table (the pointer cast to the local address space)
+    const uint32_t t = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint64_t *)tab + 13u * 8u;
+    u.x0 = t;
+    u.xm = t + (i == 3 ? 8u : 0u);
+    u.xp = t - (i == 0 ? 8u : 0u);
+    u.ym = j == 3 ? 24u : 0u;
+    u.yp = j == 0 ? uint32_t(-24) : 0u;
+    u.zm = k == 3 ? 72u : 0u;
+    u.zp = k == 0 ? uint32_t(-72) : 0u;
+    u.own = (uint32_t)(i + 4 * j + 16 * k) * (uint32_t)sizeof(T);
+    return u;
 }
 
 template <typename Lt, typename ST, int P>
-__device__ __forceinline__ void gather_interior(const int32_t *nb, int i, int j, int k,
-                                                const typename ST::T *f, typename ST::R *g) {
+__device__ __forceinline__ void gather_interior(const InteriorLane &u, typename ST::R *g) {
     if constexpr (P < Lt::Q) {
-        g[P] = load_g<Lt, ST>(f, interior_slot<Lt, P>(nb, i, j, k), P);
-        gather_interior<Lt, ST, P + 1>(nb, i, j, k, f, g);
+        using T = typename ST::T;
+        constexpr int cx = Lt::cx(P), cy = Lt::cy(P), cz = Lt::cz(P);
+        const uint32_t ex = cx < 0 ? u.xm : (cx > 0 ? u.xp : u.x0);
+        const uint32_t ey = cy < 0 ? u.ym : (cy > 0 ? u.yp : 0u);
+        const uint32_t ez = cz < 0 ? u.zm : (cz > 0 ? u.zp : 0u);
+        const uint64_t row = *(const __attribute__((address_space(3))) uint64_t *)(uintptr_t)(ex + ey + ez);
+        constexpr int64_t c = (int64_t)P * Lt::MB - (cx + 4 * cy + 16 * cz);
+        // a global-memory pointer, so the load is a global (not flat) load and
+        // does not hold up the waits on the LDS table reads
+        const T *a = (const T *)(const __attribute__((address_space(1))) T *)(row + u.own) + c;
+        g[P] = load_g<Lt, ST>(a, 0, P);
+        gather_interior<Lt, ST, P + 1>(u, g);
     }
+}
+
+// BGK relaxation of one cell in the shifted variables: moments, then
+// g <- g + omega (g_eq - g).  (A form with 1/rho taken once and the
+// equilibrium grouped by weight saved no time here, and the reciprocal's
+// rounding moved FP32 runs measurably further from FP64.)
+template <typename Lt, typename R>
+__device__ __forceinline__ void bgk_relax(R *g, R om, R &drho, R &ux, R &uy, R &uz, R &uu) {
+    moments_g<Lt, R>(g, drho, ux, uy, uz);
+    uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int p = 0; p < Lt::Q; p++) g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
 }
 
 // Per-workgroup staging of NBLK block descriptors; links by region slot.
@@ -209,6 +228,24 @@ __device__ void stage_blocks_by(MeshOf mesh_of, BlockStage<Lt, NBLK> &st) {
 template <typename Lt, int NBLK>
 __device__ void stage_blocks(const DevMesh &m, BlockStage<Lt, NBLK> &st) {
     stage_blocks_by<Lt, NBLK>([&](int) -> const DevMesh & { return m; }, st);
+}
+
+// Fill the row tables of the NBLK staged blocks (row(r) - 4 r . (1, 4, 16)
+// in elements, as addresses; 0 where the link is not a block)
+template <typename Lt, int NBLK, typename MeshOf, typename SrcOf>
+__device__ __forceinline__ void fill_row_tables(const BlockStage<Lt, NBLK> &st, MeshOf mesh_of, SrcOf src_of,
+                                                uint64_t (*tab)[27]) {
+    for (int e = threadIdx.x; e < NBLK * 27; e += blockDim.x) {
+        const int s = e / 27, r = e - s * 27;
+        const int32_t id = st.id[s] >= 0 ? st.link[s][r] : -1;
+        uint64_t v = 0;
+        if (id >= 0 && id < mesh_of(s).cap) {
+            const int rx = r % 3 - 1, ry = (r / 3) % 3 - 1, rz = r / 9 - 1;
+            const int64_t el = (int64_t)id * (Lt::Q * Lt::MB) - 4 * (rx + 4 * ry + 16 * rz);
+            v = (uint64_t)(uintptr_t)src_of(s) + (uint64_t)(el * (int64_t)sizeof(*src_of(s)));
+        }
+        tab[s][r] = v;
+    }
 }
 
 // Contiguous range of work units [u0, u1) of a persistent workgroup: the
@@ -281,7 +318,7 @@ template <int Q, int S, int NBLK, bool NTS>
 __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage<Lat<Q>, NBLK> &st, int s, int l,
                                               const typename Store<S>::T *__restrict__ src,
                                               typename Store<S>::T *__restrict__ dst, typename Store<S>::R om,
-                                              const BCParams &bc) {
+                                              const BCParams &bc, const uint64_t *tab) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
@@ -296,27 +333,20 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
     R drho, ux, uy, uz;
     if constexpr (Lt::D == 3) {
         // Interior block (every region link a same-level block): one block per
-        // wave, so the links are wave-uniform and every source is a select.
+        // wave; sources through the wave's row table (tab, in LDS).
         if (!(flag & (BF_BOUNDARY | BF_NSKIP))) {
-            int32_t nb[27];
-            uniform_links<0>(link, nb);
-            gather_interior<Lt, ST, 0>(nb, i, j, k, src, g);
-            moments_g<Lt, R>(g, drho, ux, uy, uz);
-            const R uu = ux * ux + uy * uy + uz * uz;
-            const int Bu = nb[13];
+            gather_interior<Lt, ST, 0>(interior_lane<typename ST::T>(tab, i, j, k), g);
+            R uu;
+            bgk_relax<Lt, R>(g, om, drho, ux, uy, uz, uu);
+            const int Bu = __builtin_amdgcn_readfirstlane(B);
 #pragma unroll
-            for (int p = 0; p < Q; p++) {
-                g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
-                store_g<Lt, ST, NTS>(dst, mslot<Lt>(Bu, p, l), p, g[p]);
-            }
+            for (int p = 0; p < Q; p++) store_g<Lt, ST, NTS>(dst, mslot<Lt>(Bu, p, l), p, g[p]);
             return;
         }
     }
     gather_cell<Lt, ST>(m, link, B, h, l, src, g);
-    moments_g<Lt, R>(g, drho, ux, uy, uz);
-    const R uu = ux * ux + uy * uy + uz * uz;
-#pragma unroll
-    for (int p = 0; p < Q; p++) g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
+    R uu;
+    bgk_relax<Lt, R>(g, om, drho, ux, uy, uz, uu);
 
 #pragma unroll
     for (int q = 0; q < Q; q++) {
@@ -362,20 +392,30 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
 template <int S>
 constexpr int collide_threads() { return 256; }
 
+// blocks per workgroup of k_collide_stream (one per 64-lane group)
+template <int Q, int S>
+constexpr int collide_blocks_per_wg() { return collide_threads<S>() / Lat<Q>::MB; }
+
 template <int Q, int S, bool NTS>
 __global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
     const int32_t *__restrict__ list, int n, DevMesh m, const typename Store<S>::T *__restrict__ src,
     typename Store<S>::T *__restrict__ dst, double omega_d, BCParams bc) {
     using Lt = Lat<Q>;
     using R = typename Store<S>::R;
-    constexpr int MB = Lt::MB, BPW = collide_threads<S>() / MB;
+    constexpr int MB = Lt::MB, BPW = collide_blocks_per_wg<Q, S>();
     __shared__ BlockStage<Lt, BPW> st;
+    __shared__ uint64_t tab[Lt::D == 3 ? BPW : 1][27];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int base = wg * BPW;
     if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
     __syncthreads();
     stage_blocks<Lt, BPW>(m, st);
-    collide_block<Q, S, BPW, NTS>(m, st, threadIdx.x / MB, threadIdx.x % MB, src, dst, R(omega_d), bc);
+    if constexpr (Lt::D == 3) {
+        fill_row_tables<Lt, BPW>(st, [&](int) -> const DevMesh & { return m; }, [&](int) { return src; }, tab);
+        __syncthreads();
+    }
+    const int s = threadIdx.x / MB;
+    collide_block<Q, S, BPW, NTS>(m, st, s, threadIdx.x % MB, src, dst, R(omega_d), bc, tab[Lt::D == 3 ? s : 0]);
 }
 
 // Batched form: level L of every simulation of a batch in one persistent
@@ -391,6 +431,7 @@ __global__ __launch_bounds__(NT) void k_collide_stream_batch(const SimDesc *__re
     using T = typename ST::T;
     constexpr int MB = Lt::MB, BPW = NT / MB;
     __shared__ BlockStage<Lt, BPW> st;
+    __shared__ uint64_t tab[Lt::D == 3 ? BPW : 1][27];
     const int n = *count;
     int u0, u1;
     persistent_range((n + BPW - 1) / BPW, u0, u1);
@@ -404,6 +445,11 @@ __global__ __launch_bounds__(NT) void k_collide_stream_batch(const SimDesc *__re
         }
         __syncthreads();
         stage_blocks_by<Lt, BPW>([&](int e) -> const DevMesh & { return sims[st.sim[e]].m; }, st);
+        if constexpr (Lt::D == 3) {
+            fill_row_tables<Lt, BPW>(st, [&](int e) -> const DevMesh & { return sims[st.sim[e]].m; },
+                                     [&](int e) { return (const T *)sims[st.sim[e]].f[par]; }, tab);
+            __syncthreads();
+        }
         const int tid = opaque_tid();
         const int s = tid / MB;
         int sim = st.sim[s];
@@ -411,7 +457,7 @@ __global__ __launch_bounds__(NT) void k_collide_stream_batch(const SimDesc *__re
         CSimDesc *cs = const_view(sims) + sim;
         const DevMesh m = load_mesh(cs);
         collide_block<Q, S, BPW, false>(m, st, s, tid % MB, (const T *)cs->f[par], (T *)cs->f[1 - par],
-                                 R(cs->lp.omega[L]), sims[sim].bc);
+                                 R(cs->lp.omega[L]), sims[sim].bc, tab[Lt::D == 3 ? s : 0]);
         __syncthreads();
     }
 }
@@ -1376,7 +1422,8 @@ static void collide_stream_nts(const Ctx &c, const int32_t *list, int n, int L, 
                                const BCParams &bc) {
     using T = typename Store<S>::T;
     const int sp = lp.par[L];
-    const int grid = (n + collide_threads<S>() / c.mb - 1) / (collide_threads<S>() / c.mb);
+    constexpr int bpw = collide_blocks_per_wg<Q, S>();
+    const int grid = (n + bpw - 1) / bpw;
     const T *src = (const T *)c.f[sp];
     T *dst = (T *)c.f[1 - sp];
     if ((int64_t)n * Q * c.mb * (int64_t)sizeof(T) > c.stream_bytes)
