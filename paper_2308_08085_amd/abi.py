@@ -150,6 +150,9 @@ class AmrLbm:
         base = self.arena.data_ptr()
         aligned = (base + 255) & ~255
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        # the arena comes from torch's caching allocator on the current stream:
+        # order the library stream after work pending there (a recycled block)
+        self.stream.wait_stream(torch.cuda.current_stream(device))
         h = C.c_void_p(0)
         _check(lib.amr_create(C.byref(cfg), C.c_void_p(aligned), C.c_uint64(self.arena_bytes),
                               C.c_void_p(self.stream.cuda_stream), C.byref(h)))
@@ -304,6 +307,7 @@ class AmrBatch:
         self.arena = torch.empty(self.arena_bytes + 256, dtype=torch.uint8, device=device)
         aligned = (self.arena.data_ptr() + 255) & ~255
         self.stream = self.sims[0].stream
+        self.stream.wait_stream(torch.cuda.current_stream(device))  # as in AmrLbm: the arena may be recycled
         h = C.c_void_p(0)
         _check(lib.amr_batch_create(handles, len(self.sims), C.c_void_p(aligned), C.c_uint64(self.arena_bytes),
                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)))

@@ -157,8 +157,9 @@ __device__ __forceinline__ InteriorLane interior_lane(const uint64_t *tab, int i
     return u;
 }
 
-template <typename Lt, typename ST, int P>
-__device__ __forceinline__ void gather_interior(const InteriorLane &u, typename ST::R *g) {
+// out[p] = conv(stored value of population p, p) for every population
+template <typename Lt, typename ST, int P, typename Out, typename Conv>
+__device__ __forceinline__ void gather_interior_by(const InteriorLane &u, Out *out, Conv conv) {
     if constexpr (P < Lt::Q) {
         using T = typename ST::T;
         constexpr int cx = Lt::cx(P), cy = Lt::cy(P), cz = Lt::cz(P);
@@ -170,9 +171,16 @@ __device__ __forceinline__ void gather_interior(const InteriorLane &u, typename 
         // a global-memory pointer, so the load is a global (not flat) load and
         // does not hold up the waits on the LDS table reads
         const T *a = (const T *)(const __attribute__((address_space(1))) T *)(row + u.own) + c;
-        g[P] = load_g<Lt, ST>(a, 0, P);
-        gather_interior<Lt, ST, P + 1>(u, g);
+        out[P] = conv(ST::ld(a), P);
+        gather_interior_by<Lt, ST, P + 1>(u, out, conv);
     }
+}
+
+// the shifted populations g (as load_g)
+template <typename Lt, typename ST>
+__device__ __forceinline__ void gather_interior(const InteriorLane &u, typename ST::R *g) {
+    using R = typename ST::R;
+    gather_interior_by<Lt, ST, 0>(u, g, [](R v, int p) { return ST::shift ? v : v - R(Lt::w(p)); });
 }
 
 // BGK relaxation of one cell in the shifted variables: moments, then
@@ -335,7 +343,7 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
         // Interior block (every region link a same-level block): one block per
         // wave; sources through the wave's row table (tab, in LDS).
         if (!(flag & (BF_BOUNDARY | BF_NSKIP))) {
-            gather_interior<Lt, ST, 0>(interior_lane<typename ST::T>(tab, i, j, k), g);
+            gather_interior<Lt, ST>(interior_lane<typename ST::T>(tab, i, j, k), g);
             R uu;
             bgk_relax<Lt, R>(g, om, drho, ux, uy, uz, uu);
             const int Bu = __builtin_amdgcn_readfirstlane(B);
@@ -757,7 +765,8 @@ constexpr int avg_children() { return Lat<Q>::D == 3 ? 4 : Lat<Q>::NC; }
 template <int Q, int S>
 __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, const typename Store<S>::T *src,
                                                typename Store<S>::T *dst, typename Store<S>::R r, int all_cells,
-                                               BlockStage<Lat<Q>, avg_children<Q>() + 1> &st, int t) {
+                                               BlockStage<Lat<Q>, avg_children<Q>() + 1> &st,
+                                               uint64_t (*tab)[27], int t) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
@@ -766,6 +775,10 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, 
     if (t <= NCW) st.id[t] = t < NCW ? first + c0 + t : P;
     __syncthreads();
     stage_blocks<Lt, NCW + 1>(m, st);
+    if constexpr (Lt::D == 3) {
+        fill_row_tables<Lt, NCW + 1>(st, [&](int) -> const DevMesh & { return m; }, [&](int) { return src; }, tab);
+        __syncthreads();
+    }
     const int cw = t / MB, lf = t - cw * MB;
     if (cw >= NCW) return;
     const int c = c0 + cw;  // octant of the child in its parent
@@ -778,7 +791,14 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, 
     const int lead = lf & ~(Lt::D == 3 ? 0x15 : 0x5);
     R g[Q];
     if ((im >> lead) & 1ull) {
-        gather_cell_flag<Lt, ST>(m, st.link[cw], child, st.hid[cw], st.flag[cw], lf, src, g);
+        bool done = false;
+        if constexpr (Lt::D == 3) {
+            if (!(st.flag[cw] & (BF_BOUNDARY | BF_NSKIP))) {
+                gather_interior<Lt, ST>(interior_lane<typename ST::T>(tab[cw], lf & 3, (lf >> 2) & 3, lf >> 4), g);
+                done = true;
+            }
+        }
+        if (!done) gather_cell_flag<Lt, ST>(m, st.link[cw], child, st.hid[cw], st.flag[cw], lf, src, g);
     } else {
 #pragma unroll
         for (int p = 0; p < Q; p++) g[p] = R(0);
@@ -813,13 +833,14 @@ __global__ __launch_bounds__(256) void k_average(const int32_t *__restrict__ lis
     using R = typename Store<S>::R;
     constexpr int SPLIT = Lt::NC / avg_children<Q>();
     __shared__ BlockStage<Lt, avg_children<Q>() + 1> st;
+    __shared__ uint64_t tab[Lt::D == 3 ? avg_children<Q>() + 1 : 1][27];
     const int item = blockIdx.x / SPLIT, part = blockIdx.x % SPLIT;
     if (item >= n) return;
     const int P = list[item];
     if (!average_target(m, P, Lt::NC)) return;
     const int L = m.level[P];
     average_parent<Q, S>(m, P, part * avg_children<Q>(), lp.par[L + 1] ? f1 : f0, lp.par[L] ? f1 : f0,
-                         R(lp.r_fc[L]), all_cells, st, threadIdx.x);
+                         R(lp.r_fc[L]), all_cells, st, tab, threadIdx.x);
 }
 
 // Batched interface averaging of level L+1 into level L, persistent
@@ -834,6 +855,7 @@ __global__ __launch_bounds__(256) void k_average_batch(const SimDesc *__restrict
     using T = typename ST::T;
     constexpr int SPLIT = Lt::NC / avg_children<Q>();
     __shared__ BlockStage<Lt, avg_children<Q>() + 1> st;
+    __shared__ uint64_t tab[Lt::D == 3 ? avg_children<Q>() + 1 : 1][27];
     int u0, u1;
     persistent_range(*count * SPLIT, u0, u1);
     for (int u = u0; u < u1; u++) {
@@ -845,7 +867,7 @@ __global__ __launch_bounds__(256) void k_average_batch(const SimDesc *__restrict
         const DevMesh m = load_mesh(cs);
         if (average_target(m, P, Lt::NC))
             average_parent<Q, S>(m, P, (u % SPLIT) * avg_children<Q>(), (const T *)cs->f[par1], (T *)cs->f[par0],
-                                 R(cs->lp.r_fc[L]), 0, st, opaque_tid());
+                                 R(cs->lp.r_fc[L]), 0, st, tab, opaque_tid());
         __syncthreads();
     }
 }
@@ -1073,11 +1095,27 @@ __global__ __launch_bounds__(256) void k_velocity(const int32_t *__restrict__ li
     if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
     __syncthreads();
     stage_blocks<Lt, BPW>(m, st);
+    __shared__ uint64_t tab[Lt::D == 3 ? BPW : 1][27];
+    if constexpr (Lt::D == 3) {
+        fill_row_tables<Lt, BPW>(st, [&](int) -> const DevMesh & { return m; }, [&](int) { return f; }, tab);
+        __syncthreads();
+    }
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
     const int B = st.id[s];
     if (B < 0) return;
     double fv[Q];
-    cell_f64<Lt, ST>(m, st.link[s], B, st.hid[s], l, f, fv);
+    bool done = false;
+    if constexpr (Lt::D == 3) {
+        if (!(st.flag[s] & (BF_BOUNDARY | BF_NSKIP))) {
+            // the same values as cell_f64, through the row table
+            gather_interior_by<Lt, ST, 0>(interior_lane<typename ST::T>(tab[s], l & 3, (l >> 2) & 3, l >> 4), fv,
+                                          [](typename ST::R v, int p) {
+                                              return double(v) + (ST::shift ? Lt::w(p) : 0.0);
+                                          });
+            done = true;
+        }
+    }
+    if (!done) cell_f64<Lt, ST>(m, st.link[s], B, st.hid[s], l, f, fv);
     double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int p = 0; p < Q; p++) {
@@ -1104,12 +1142,16 @@ __global__ __launch_bounds__(256) void k_vorticity(const int32_t *__restrict__ l
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
     const int B = st.id[s];
     const bool leaf = B >= 0 && m.status[B] == ST_UNREF;
+    // the velocities of the block's own cells, for the neighbours inside it
+    __shared__ double us[BPW][3][MB];
+    if (leaf)
+        for (int b = 0; b < 3; b++) us[s][b][l] = U[b * m.capc + (int64_t)B * MB + l];
+    __syncthreads();
     double w = 0.0;
     if (leaf) {
         const int ci[3] = {l & 3, (l >> 2) & 3, l >> 4};
-        const int64_t cell = (int64_t)B * MB + l;
         double u0[3];
-        for (int b = 0; b < 3; b++) u0[b] = U[b * m.capc + cell];
+        for (int b = 0; b < 3; b++) u0[b] = us[s][b][l];
         double gr[3][3];
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) gr[a][b] = 0.0;
@@ -1119,11 +1161,17 @@ __global__ __launch_bounds__(256) void k_vorticity(const int32_t *__restrict__ l
             for (int sg = 0; sg < 2; sg++) {
                 int t[3] = {ci[0], ci[1], ci[2]};
                 t[a] += sg == 0 ? 1 : -1;
-                const int32_t code = st.link[s][region_of<Lt>(t[0], t[1], t[2])];
+                const int rg = region_of<Lt>(t[0], t[1], t[2]);
+                const int32_t code = st.link[s][rg];
                 if (code < 0 || code >= m.cap) continue;
-                const int64_t nc = (int64_t)code * MB + (t[0] & 3) + 4 * (t[1] & 3) + 16 * (t[2] & 3);
+                const int lc = (t[0] & 3) + 4 * (t[1] & 3) + 16 * (t[2] & 3);
                 double *dstv = sg == 0 ? up : um;
-                for (int b = 0; b < 3; b++) dstv[b] = U[b * m.capc + nc];
+                if (rg == kCenterSlot<Lt>) {
+                    for (int b = 0; b < 3; b++) dstv[b] = us[s][b][lc];
+                } else {
+                    const int64_t nc = (int64_t)code * MB + lc;
+                    for (int b = 0; b < 3; b++) dstv[b] = U[b * m.capc + nc];
+                }
                 if (sg == 0) hp = true; else hm = true;
             }
             for (int b = 0; b < 3; b++) {
