@@ -74,14 +74,17 @@ def log(*a):
 
 
 def run_storage(case, storage, steps, warmup, theta, profile_periods=2, graph=True, tag_kind=None,
-                keep_state=False):
+                keep_state=False, collision=None):
     """keep_state: also return the tags of every adaptation and the final rho/u
-    of the output cells (for the error leg)"""
+    of the output cells (for the error leg); collision: (kind, s_high) for
+    amr_set_collision, else BGK"""
     import torch
     from paper_2308_08085_amd import abi, workloads as W
 
     g = abi.AmrLbm(case, storage=storage)
     g.set_root_rho_u(case.initial_rho_u())
+    if collision is not None:
+        g.set_collision(*collision)
     for _ in range(case.dist_levels):  # static near-wall refinement at t = 0
         g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=1)
         g.adapt()
@@ -576,6 +579,19 @@ def main():
                                          "adapt_ms_per_cycle": round(rl["adapt_ms_per_cycle"], 3),
                                          "adaptations_refused_for_capacity": rl["adaptations_refused_for_capacity"],
                                          "level_blocks_end": rl["level_blocks"]}}
+        # moment-space collision (D3Q27; higher moments at 1.2): vector ALU and
+        # matrix-core transforms against the BGK runs above, same set-up
+        mrt = {"s_high": 1.2}
+        for st, base in (("f32s", r32), ("f16s", r16)):
+            if base is None:
+                continue
+            for name, kind in (("vector_alu", abi.COLLIDE_MRT), ("matrix_cores", abi.COLLIDE_MRT_MFMA)):
+                rm = run_storage(main_case, st, max(2, args.steps // 4), 1, theta, collision=(kind, 1.2))
+                k = rm["kernels"]["collide_stream"]
+                mrt["%s_%s" % (name, st)] = {
+                    "mlups": round(rm["mlups"], 1), "vs_bgk": round(rm["mlups"] / base["mlups"], 3),
+                    "collide_avg_us": round(k["ms"] * 1e3 / max(k["launches"], 1), 1)}
+        ext["moment_space_collision"] = mrt
     uni = None if args.no_uniform else uniform_sweep()
     if uni:
         log("[uniform] %s: %.1f MLUPS, collide %.1f GB/s" % (uni["workload"], uni["mlups"], uni["roofline"]["achieved"]))

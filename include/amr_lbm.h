@@ -262,6 +262,28 @@ enum amr_field_kind {
 };
 amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf, uint64_t bytes);
 
+/* Collision operator of the collide-stream sweeps.  The paper's method is BGK
+ * (Sec. "Collision"), the default.  It names moment-space (multiple-relaxation-
+ * time) collision as the alternative (Sec. "Lattice Boltzmann Method"); this
+ * library offers one for D3Q27 only:
+ *   AMR_COLLIDE_MRT       moments phi_a(c_x) phi_b(c_y) phi_c(c_z), phi_0 = 1,
+ *                         phi_1 = c, phi_2 = 3 c^2 - 1; density, momentum and the
+ *                         second-order moments relax at each level's omega, the
+ *                         17 higher moments at s_high; transforms on the vector
+ *                         ALU in the storage's arithmetic (FP64 or FP32);
+ *   AMR_COLLIDE_MRT_MFMA  the same operator with both high-moment transforms on
+ *                         the matrix cores (FP16 operands, FP32 accumulation);
+ *                         storages with FP32 arithmetic only.
+ * s_high = omega gives the BGK result exactly.  The interpolation and averaging
+ * rescaling stay those of BGK (Secs. "Linear Interpolation", "Averaging"), whose
+ * derivation assumes BGK.  Batches (amr_batch_create) accept BGK members only.
+ * kind: enum amr_collision; s_high in (0, 2), ignored for AMR_COLLIDE_BGK.
+ * Captured step graphs are re-captured.
+ * Errors: AMR_ERR_ARG (unknown kind, lattice other than D3Q27, FP64 storage
+ * with AMR_COLLIDE_MRT_MFMA, s_high out of range, handle in a batch). */
+enum amr_collision { AMR_COLLIDE_BGK = 0, AMR_COLLIDE_MRT = 1, AMR_COLLIDE_MRT_MFMA = 2 };
+amr_status amr_set_collision(amr_t *h, int32_t kind, double s_high);
+
 /* Release the host-side handle.  The arena stays the caller's; the stream is
  * synchronised first.  NULL is accepted. */
 amr_status amr_destroy(amr_t *h);

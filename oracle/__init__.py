@@ -67,7 +67,7 @@ def lib():
                      "orc_lattice", "orc_feq", "orc_collide", "orc_interp_child", "orc_interp_child_cubic",
                      "orc_average_parent",
                      "orc_parity", "orc_force", "orc_get_f_all", "orc_cell_classes", "orc_set_threads",
-                     "orc_ratios", "orc_sweep"):
+                     "orc_ratios", "orc_sweep", "orc_mrt_collide", "orc_mrt_matrix", "orc_set_collision"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -104,6 +104,23 @@ def collide(dim: int, q: int, omega: float, f) -> np.ndarray:
     out = np.zeros(q, np.float64)
     lib().orc_collide(dim, q, C.c_double(omega), _dp(f), _dp(out))
     return out
+
+
+def mrt_collide(omega: float, s_high: float, f) -> np.ndarray:
+    """moment-space collision of one D3Q27 cell (moments above second order at s_high)"""
+    f = np.ascontiguousarray(f, np.float64)
+    out = np.zeros(27, np.float64)
+    if lib().orc_mrt_collide(C.c_double(omega), C.c_double(s_high), _dp(f), _dp(out)) != 0:
+        raise RuntimeError("moment matrix is singular")
+    return out
+
+
+def mrt_matrix() -> np.ndarray:
+    """the D3Q27 moment matrix M[k][p] of the moment-space collision"""
+    m = np.zeros((27, 27), np.float64)
+    if lib().orc_mrt_matrix(_dp(m)) != 0:
+        raise RuntimeError("moment matrix is singular")
+    return m
 
 
 def interp_child(dim: int, q: int, r: float, parent, child: int, cubic: bool = False) -> np.ndarray:
@@ -201,6 +218,11 @@ class Oracle:
 
     def step(self, n: int = 1):
         lib().orc_step(self.h, int(n))
+
+    def set_collision(self, kind: int, s_high: float = 1.0):
+        """0 = BGK; 1 = moment-space collision (D3Q27), higher moments at s_high"""
+        if lib().orc_set_collision(self.h, int(kind), C.c_double(s_high)) != 0:
+            raise ValueError("collision kind %d with s_high %g is not available here" % (kind, s_high))
 
     def sweep(self, L: int):
         """one collide-stream sweep of level L alone (timing only: the forest is

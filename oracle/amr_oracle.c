@@ -150,6 +150,102 @@ int orc_collide(int dim, int q, double omega, const double *f, double *out)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Moment-space (multiple-relaxation-time) collision for D3Q27.  The paper
+ * uses BGK and names moment-space operators only as an alternative (Sec.
+ * "Lattice Boltzmann Method" and its review of collision operators); this is
+ * the reference for the library's optional moment-space collision.
+ * Moment k = a + 3 b + 9 c (a, b, c in 0..2) is sum_p phi_a(c_px) phi_b(c_py)
+ * phi_c(c_pz) f_p with phi_0 = 1, phi_1 = c, phi_2 = 3 c^2 - 1.  Its order
+ * counts 1 per phi_1 and 2 per phi_2 factor; moments of order <= 2 (density,
+ * momentum, stress) relax at omega, the rest at s_high:
+ *   m = M f,  m_eq = M f_eq,  f* = M^-1 (m - S (m - m_eq)),
+ * with M^-1 from Gauss-Jordan elimination.  s_high = omega gives BGK. */
+static double MRT_M[27][27], MRT_MI[27][27];
+static int mrt_ready = 0;
+
+static double mrt_phi(int a, int c)
+{
+    return a == 0 ? 1.0 : (a == 1 ? (double)c : 3.0 * c * c - 1.0);
+}
+
+static int mrt_order(int k)
+{
+    int o = 0;
+    for (int d = 0; d < 3; d++) {
+        int a = k % 3;
+        k /= 3;
+        o += a;
+    }
+    return o;
+}
+
+static int mrt_init(void)
+{
+    if (mrt_ready) return 0;
+    double A[27][54];
+    for (int k = 0; k < 27; k++)
+        for (int p = 0; p < 27; p++)
+            MRT_M[k][p] = mrt_phi(k % 3, VEC3[p][0]) * mrt_phi((k / 3) % 3, VEC3[p][1]) * mrt_phi(k / 9, VEC3[p][2]);
+    for (int i = 0; i < 27; i++)
+        for (int j = 0; j < 54; j++) A[i][j] = j < 27 ? MRT_M[i][j] : (j - 27 == i ? 1.0 : 0.0);
+    for (int col = 0; col < 27; col++) {
+        int piv = col;
+        for (int r = col + 1; r < 27; r++)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        if (fabs(A[piv][col]) < 1e-12) return -1;
+        if (piv != col)
+            for (int j = 0; j < 54; j++) { double t = A[col][j]; A[col][j] = A[piv][j]; A[piv][j] = t; }
+        double d = A[col][col];
+        for (int j = 0; j < 54; j++) A[col][j] /= d;
+        for (int r = 0; r < 27; r++) {
+            if (r == col || A[r][col] == 0.0) continue;
+            double fct = A[r][col];
+            for (int j = 0; j < 54; j++) A[r][j] -= fct * A[col][j];
+        }
+    }
+    for (int i = 0; i < 27; i++)
+        for (int j = 0; j < 27; j++) MRT_MI[i][j] = A[i][27 + j];
+    mrt_ready = 1;
+    return 0;
+}
+
+static void mrt_relax(const double *f, const double *feq, double omega, double s_high, double *out)
+{
+    double ms[27];
+    for (int k = 0; k < 27; k++) {
+        double m = 0.0, meq = 0.0;
+        for (int p = 0; p < 27; p++) {
+            m += MRT_M[k][p] * f[p];
+            meq += MRT_M[k][p] * feq[p];
+        }
+        double s = mrt_order(k) <= 2 ? omega : s_high;
+        ms[k] = m - s * (m - meq);
+    }
+    for (int p = 0; p < 27; p++) {
+        double v = 0.0;
+        for (int k = 0; k < 27; k++) v += MRT_MI[p][k] * ms[k];
+        out[p] = v;
+    }
+}
+
+int orc_mrt_matrix(double *m_out /* [27][27], row = moment */)
+{
+    if (mrt_init() != 0) return -1;
+    memcpy(m_out, MRT_M, sizeof(MRT_M));
+    return 0;
+}
+
+int orc_mrt_collide(double omega, double s_high, const double *f, double *out)
+{
+    if (mrt_init() != 0) return -1;
+    double rho, u[3], feq[27];
+    moments(3, 27, f, &rho, u);
+    equilibrium(3, 27, rho, u, feq);
+    mrt_relax(f, feq, omega, s_high, out);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Coarse-to-fine linear interpolation (Sec. "Linear Interpolation").
  * The parent's cells are rescaled first (g = feq + r (f - feq), Dupuis-Chopard);
  * fine cell (I,J,K) of child c sits at (-1/4 + I/2, -1/4 + J/2, -1/4 + K/2) in
@@ -328,6 +424,8 @@ struct orc {
     double *crit;
     double *force;          /* cap*3 momentum exchange with solid blocks since the last reset */
     double sweeps[MAXL];    /* collide-stream sweeps of each level since the last reset */
+    int coll;               /* 0 = BGK, 1 = moment-space (D3Q27) */
+    double s_high;          /* rate of the moments above second order (coll = 1) */
 };
 
 static const int *bvec(const orc_t *o, int p) { return o->dim == 2 ? VEC2[p] : VEC3[p]; }
@@ -523,6 +621,19 @@ int orc_get_f_all(orc_t *o, double *out)
     return 0;
 }
 
+int orc_set_collision(orc_t *o, int kind, double s_high)
+{
+    if (kind == 0) {
+        o->coll = 0;
+        return 0;
+    }
+    if (kind != 1 || o->dim != 3 || o->q != 27 || !(s_high > 0.0 && s_high < 2.0)) return -1;
+    if (mrt_init() != 0) return -1;
+    o->coll = 1;
+    o->s_high = s_high;
+    return 0;
+}
+
 int orc_set_threads(int n)
 {
 #ifdef _OPENMP
@@ -644,7 +755,10 @@ static void collide_stream_level(orc_t *o, int L)
             double rho, u[3], feq[27], fs[27];
             moments(o->dim, q, fc, &rho, u);
             equilibrium(o->dim, q, rho, u, feq);
-            for (int p = 0; p < q; p++) fs[p] = (1.0 - omega) * fc[p] + omega * feq[p];
+            if (o->coll == 1)
+                mrt_relax(fc, feq, omega, o->s_high, fs);
+            else
+                for (int p = 0; p < q; p++) fs[p] = (1.0 - omega) * fc[p] + omega * feq[p];
             double *own = cellf(o, dst, B, l);
             for (int p = 0; p < q; p++) {
                 const int *c = o->dim == 2 ? VEC2[p] : VEC3[p];

@@ -58,6 +58,9 @@ int orc_lattice(int dim, int q, int32_t *c, double *w, int32_t *opp);
 int orc_feq(int dim, int q, double rho, const double *u, double *out);
 /* BGK collision of a single cell with relaxation rate omega */
 int orc_collide(int dim, int q, double omega, const double *f, double *out);
+/* moment-space collision of one D3Q27 cell (see orc_set_collision) and its moment matrix [27][27] */
+int orc_mrt_collide(double omega, double s_high, const double *f, double *out);
+int orc_mrt_matrix(double *m_out);
 /* linear interpolation of all cells of child c of a parent block; parent[Mb*q], out[Mb*q] (cell-major) */
 int orc_interp_child(int dim, int q, double r, const double *parent, int child, double *out);
 /* the same with cubic interpolation (Sec. "Cubic Interpolation") */
@@ -78,6 +81,9 @@ int orc_get_f_all(orc_t *o, double *out);
 int orc_cell_classes(orc_t *o, int32_t B, int32_t *out);
 /* host threads of the per-block loops (n <= 0: unchanged); returns the count in use */
 int orc_set_threads(int n);
+/* collision of the sweeps: kind 0 = BGK (default), 1 = moment-space, D3Q27
+ * only, moments above second order relaxing at s_high in (0, 2) */
+int orc_set_collision(orc_t *o, int kind, double s_high);
 int orc_step(orc_t *o, int32_t n_coarse_steps);
 /* one collide-stream sweep of level L alone (for timing; leaves the forest mid-step) */
 int orc_sweep(orc_t *o, int32_t L);

@@ -22,12 +22,13 @@ AMR_GET, AMR_SET = 0, 1
  F_COUNTS, F_MASS_MOM, F_CRIT, F_PARITY, F_KERNEL_STATS, F_FORCE, F_FORCE_ON, F_STREAM_BYTES) = range(20)
 AMR_CHECK_FINITE, AMR_USE_GRAPH, AMR_PROFILE = 1, 2, 4
 TAG_VORTICITY_REL, TAG_DISTANCE, TAG_LADDER = 0, 1, 2
+COLLIDE_BGK, COLLIDE_MRT, COLLIDE_MRT_MFMA = 0, 1, 2
 
 # every symbol the header declares
 EXPORTS = ("amr_query_bytes", "amr_create", "amr_tag", "amr_adapt", "lbm_step", "amr_fields", "amr_destroy",
            "amr_batch_query_bytes", "amr_batch_create", "amr_batch_step", "amr_batch_set_tuning",
            "amr_batch_get_tuning", "amr_batch_autotune", "amr_batch_destroy", "amr_mass_mom_static",
-           "amr_last_error")
+           "amr_set_collision", "amr_last_error")
 
 
 class AmrError(RuntimeError):
@@ -88,6 +89,7 @@ def load():
         L.amr_batch_autotune.argtypes = [P, C.c_int32, C.POINTER(BatchTuning), C.POINTER(C.c_double)]
         L.amr_batch_destroy.argtypes = [P]
         L.amr_mass_mom_static.argtypes = [P, P]
+        L.amr_set_collision.argtypes = [P, C.c_int32, C.c_double]
         L.amr_last_error.restype = C.c_char_p
         for n in EXPORTS[:-1]:
             getattr(L, n).restype = C.c_int32
@@ -253,6 +255,11 @@ class AmrLbm:
         if value is not None:
             self._fields(AMR_SET, F_STREAM_BYTES, np.array([int(value)], np.int64))
         return int(self._fields(AMR_GET, F_STREAM_BYTES, np.zeros(1, np.int64))[0])
+
+    def set_collision(self, kind, s_high=1.0):
+        """amr_set_collision: COLLIDE_BGK, COLLIDE_MRT or COLLIDE_MRT_MFMA (D3Q27),
+        the moments above second order relaxing at s_high"""
+        _check(load().amr_set_collision(self._h, int(kind), C.c_double(s_high)))
 
     def mass_mom_static(self, out_dev):
         """amr_mass_mom_static: enqueue the mass/momentum sums into the caller's

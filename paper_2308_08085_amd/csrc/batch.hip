@@ -82,11 +82,11 @@ namespace {
 
 amr_status validate_members(amr_t *const *sims, int n, void *stream) {
     if (!sims || n < 1) return fail(AMR_ERR_ARG, "a batch needs at least one simulation");
-    std::vector<Group> groups;
-    plan_groups(sims, n, groups);
     for (int i = 0; i < n; i++) {
         const amr_t *h = sims[i];
         if (!h) return fail(AMR_ERR_ARG, "simulation %d is NULL", i);
+        if (h->c.coll != AMR_COLLIDE_BGK)
+            return fail(AMR_ERR_ARG, "simulation %d uses a moment-space collision; batches advance BGK members only", i);
         for (int j = 0; j < i; j++)
             if (sims[j] == h) return fail(AMR_ERR_ARG, "simulation %d appears twice", i);
         if (h->c.stream != (hipStream_t)stream)
@@ -99,6 +99,8 @@ amr_status validate_members(amr_t *const *sims, int n, void *stream) {
         for (int L = 1; L < h->lmax; L++)
             if (h->par[L] != 0) return fail(AMR_ERR_STATE, "simulation %d is inside a coarse step", i);
     }
+    std::vector<Group> groups;
+    plan_groups(sims, n, groups);
     for (auto &g : groups)
         if ((int)g.members.size() > kMaxBatchSims)
             return fail(AMR_ERR_ARG, "more than %d simulations of one lattice and storage", kMaxBatchSims);
@@ -284,6 +286,7 @@ amr_status amr_batch_create(amr_t *const *sims, int32_t n, void *dev_arena, uint
                     (unsigned long long)arena_bytes, (unsigned long long)need);
     }
     b->sims.assign(sims, sims + n);
+    for (int i = 0; i < n; i++) sims[i]->batches++;
     b->stream = (hipStream_t)hip_stream;
     b->par0 = sims[0]->par[0];
     b->tune.threads = 256;
@@ -426,6 +429,7 @@ amr_status amr_batch_destroy(amr_batch_t *b) {
         hipStreamDestroy(st);
     }
     for (auto ev : b->ev) hipEventDestroy(ev);
+    for (auto h : b->sims) h->batches--;
     delete b;
     return AMR_OK;
 }

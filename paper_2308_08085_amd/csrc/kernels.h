@@ -60,6 +60,8 @@ struct Ctx {
     void *staging;
     size_t staging_bytes;
     int64_t stream_bytes;  // sweeps writing more than this use non-temporal stores
+    int coll;              // enum amr_collision of the collide-stream sweeps
+    double s_high;         // moment-space collision: rate of the moments above second order
     hipStream_t stream;
 };
 

@@ -195,6 +195,173 @@ __device__ __forceinline__ void bgk_relax(R *g, R om, R &drho, R &ux, R &uy, R &
     for (int p = 0; p < Lt::Q; p++) g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
 }
 
+// ---------------------------------------------------------------------------
+// Moment-space (multiple-relaxation-time) collision for D3Q27, optional: the
+// paper's method is BGK and it names moment-space operators only as the
+// alternative (Sec. "Lattice Boltzmann Method").  Moment k = a + 3 b + 9 c is
+// sum_p phi_a(c_x) phi_b(c_y) phi_c(c_z) f_p with phi_0 = 1, phi_1 = c,
+// phi_2 = 3 c^2 - 1; the rows are orthogonal under the lattice weights with
+// norms N_k = n_a n_b n_c (n = 1, 1/3, 2), so M^-1 = diag(w) M^T diag(1/N).
+// Moments of order <= 2 relax at omega, the 17 others at s_high.  With the
+// non-equilibrium part n = g - g_eq this is BGK plus a correction in the high
+// moments only:
+//     g* = g - omega n - w_p sum_{k high} M_kp ((s_high - omega) / N_k) (M n)_k
+// so s_high = omega gives the BGK arithmetic exactly.
+struct Mrt27 {
+    static constexpr int NH = 17;
+    int hk[NH];  // the moments of order > 2, ascending
+    static constexpr int order(int k) { return k % 3 + k / 3 % 3 + k / 9; }
+    static constexpr int phi(int a, int c) { return a == 0 ? 1 : (a == 1 ? c : 3 * c * c - 1); }
+    static constexpr int m(int k, int p) { return phi(k % 3, D3::cx(p)) * phi(k / 3 % 3, D3::cy(p)) * phi(k / 9, D3::cz(p)); }
+    static constexpr double norm(int k) {
+        return (k % 3 == 0 ? 1.0 : (k % 3 == 1 ? 1.0 / 3.0 : 2.0)) *
+               (k / 3 % 3 == 0 ? 1.0 : (k / 3 % 3 == 1 ? 1.0 / 3.0 : 2.0)) *
+               (k / 9 == 0 ? 1.0 : (k / 9 == 1 ? 1.0 / 3.0 : 2.0));
+    }
+    constexpr Mrt27() : hk() {
+        int n = 0;
+        for (int k = 0; k < 27; k++)
+            if (order(k) > 2) hk[n++] = k;
+    }
+};
+constexpr Mrt27 kMrt27{};
+
+// g -= w_p sum_k M_kp fac h_k / N_k with h = M n over the high moments, on the
+// vector ALU (every coefficient a compile-time constant)
+template <typename R, int S = 0>
+__device__ __forceinline__ void mrt27_high(const R *n, R fac, R *g) {
+    if constexpr (S < Mrt27::NH) {
+        constexpr int k = kMrt27.hk[S];
+        R h = R(0);
+#pragma unroll
+        for (int p = 0; p < 27; p++)
+            if constexpr (true) {
+                const int c = Mrt27::m(k, p);
+                if (c == 1) h += n[p];
+                else if (c == -1) h -= n[p];
+                else if (c != 0) h += R(c) * n[p];
+            }
+        h *= fac * R(1.0 / Mrt27::norm(k));
+#pragma unroll
+        for (int p = 0; p < 27; p++) {
+            const int c = Mrt27::m(k, p);
+            if (c != 0) g[p] -= R(Lat<27>::w(p) * c) * h;
+        }
+        mrt27_high<R, S + 1>(n, fac, g);
+    }
+}
+
+// The same correction with both transforms on the matrix cores
+// (v_mfma_f32_16x16x32_f16; FP16 operands, FP32 accumulation).  One wave, 64
+// cells = four tiles of 16.  Lane layout of the instruction: A[i][k] at lane l
+// for i = l % 16, k = 8 (l / 16) + e (e = 0..7); B[k][j] for j = l % 16, the same
+// k; D[i][j] in register r of lane l for i = 4 (l / 16) + r, j = l % 16.
+//   forward:  H = M_high N   (rows: 32 slots, the 17 high moments first;
+//                             K: the 27 populations; columns: cells)
+//   scale:    slot s by (s_high - omega) / N_k, to FP16
+//   back:     C = M_high^T H' (rows: populations; K in the order in which each
+//             lane already holds the forward result: k = 8 g + e is slot
+//             4 g + e for e < 4 and 16 + 4 g + e - 4 otherwise, g = l / 16)
+// N is scaled by 2^8 before rounding to FP16 (non-equilibrium parts are small)
+// and C by 2^-8 after.  The cell-major transposes go through LDS.
+typedef _Float16 mf_h8 __attribute__((ext_vector_type(8)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+struct MrtMfmaOps {
+    _Float16 af[2][64][8];  // forward A, row blocks 0 / 1, per lane
+    _Float16 ab[2][64][8];  // back A, population blocks 0 / 1, per lane
+    float invn[32];         // 1 / N of the slot's moment; 0 past the 17
+    static constexpr int slot_of_back_k(int k) { return (k % 8) < 4 ? 4 * (k / 8) + k % 8 : 16 + 4 * (k / 8) + k % 8 - 4; }
+    constexpr MrtMfmaOps() : af(), ab(), invn() {
+        for (int s = 0; s < 32; s++) invn[s] = s < Mrt27::NH ? float(1.0 / Mrt27::norm(kMrt27.hk[s])) : 0.0f;
+        for (int b = 0; b < 2; b++)
+            for (int l = 0; l < 64; l++)
+                for (int e = 0; e < 8; e++) {
+                    const int i = l % 16, k = 8 * (l / 16) + e;
+                    const int sf = 16 * b + i;  // forward: row = slot, K = population
+                    af[b][l][e] = (_Float16)((sf < Mrt27::NH && k < 27) ? Mrt27::m(kMrt27.hk[sf], k) : 0);
+                    const int p = 16 * b + i, sb = slot_of_back_k(k);  // back: row = population
+                    ab[b][l][e] = (_Float16)((sb < Mrt27::NH && p < 27) ? Mrt27::m(kMrt27.hk[sb], p) : 0);
+                }
+    }
+};
+constexpr MrtMfmaOps kMrtMfma{};
+
+__device__ __forceinline__ void mrt27_high_mfma(const float *n, float fac, float *g) {
+    constexpr float kScale = 256.0f;
+    // per wave: 64 cells x 36 words (FP16 rows of 32 for the forward pass, FP32 rows of 32 for the back pass)
+    __shared__ __attribute__((aligned(16))) float buf[4][64 * 36];
+    const int l = threadIdx.x & 63, grp = l >> 4, col = l & 15;
+    float *wb = buf[threadIdx.x >> 6];
+    _Float16 *hb = (_Float16 *)wb;
+    // cell-major FP16 rows of the scaled non-equilibrium parts: [cell][32]
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        mf_h8 v;
+#pragma unroll
+        for (int e = 0; e < 8; e++) v[e] = (_Float16)(8 * c + e < 27 ? n[8 * c + e] * kScale : 0.0f);
+        *(mf_h8 *)(hb + l * 72 + 8 * c) = v;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    mf_h8 af0, af1, ab0, ab1;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        af0[e] = kMrtMfma.af[0][l][e];
+        af1[e] = kMrtMfma.af[1][l][e];
+        ab0[e] = kMrtMfma.ab[0][l][e];
+        ab1[e] = kMrtMfma.ab[1][l][e];
+    }
+    float fs[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) fs[e] = fac * kMrtMfma.invn[e < 4 ? 4 * grp + e : 16 + 4 * grp + e - 4];
+    const mf_f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    mf_h8 bb[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const mf_h8 b = *(const mf_h8 *)(hb + (16 * t + col) * 72 + 8 * grp);
+        const mf_f4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(af0, b, zero, 0, 0, 0);
+        const mf_f4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(af1, b, zero, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 8; e++) bb[t][e] = (_Float16)((e < 4 ? d0[e] : d1[e - 4]) * fs[e]);
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const mf_f4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ab0, bb[t], zero, 0, 0, 0);
+        const mf_f4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ab1, bb[t], zero, 0, 0, 0);
+        // populations 4 grp + r and 16 + 4 grp + r of cell 16 t + col
+        *(mf_f4 *)(wb + (16 * t + col) * 36 + 4 * grp) = c0;
+        *(mf_f4 *)(wb + (16 * t + col) * 36 + 16 + 4 * grp) = c1;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int p = 0; p < 27; p++) g[p] -= float(Lat<27>::w(p) / 256.0) * wb[l * 36 + p];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// Collision of one cell: COLL 0 = BGK, 1 = moment-space on the vector ALU,
+// 2 = moment-space with the high-moment transforms on the matrix cores (a
+// whole wave, every lane active; mrt27_high_mfma).
+template <typename Lt, typename R, int COLL>
+__device__ __forceinline__ void relax(R *g, R om, R sh, R &drho, R &ux, R &uy, R &uz, R &uu) {
+    if constexpr (COLL == 0 || Lt::Q != 27) {
+        bgk_relax<Lt, R>(g, om, drho, ux, uy, uz, uu);
+    } else {
+        moments_g<Lt, R>(g, drho, ux, uy, uz);
+        uu = ux * ux + uy * uy + uz * uz;
+        R n[27];
+#pragma unroll
+        for (int p = 0; p < 27; p++) {
+            n[p] = g[p] - geq<Lt, R>(p, drho, ux, uy, uz, uu);
+            g[p] -= om * n[p];
+        }
+        if constexpr (COLL == 1)
+            mrt27_high<R>(n, sh - om, g);
+        else if constexpr (sizeof(R) == 4)
+            mrt27_high_mfma(n, sh - om, g);
+    }
+}
+
 // Per-workgroup staging of NBLK block descriptors; links by region slot.
 // sim[] names the simulation of each entry in the batched kernels.
 template <typename Lt, int NBLK>
@@ -322,11 +489,12 @@ __device__ inline void decode_item(uint32_t it, int &sim, int &B) {
 // post-collision value (halo record).  NTS: write with non-temporal stores
 // (for levels whose output is too large to stay cached until the next sweep).
 // Body: the cells of staged block s (this thread: cell l).
-template <int Q, int S, int NBLK, bool NTS>
+template <int Q, int S, int NBLK, bool NTS, int COLL = 0>
 __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage<Lat<Q>, NBLK> &st, int s, int l,
                                               const typename Store<S>::T *__restrict__ src,
                                               typename Store<S>::T *__restrict__ dst, typename Store<S>::R om,
-                                              const BCParams &bc, const uint64_t *tab) {
+                                              const BCParams &bc, const uint64_t *tab,
+                                              typename Store<S>::R sh = typename Store<S>::R(0)) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
@@ -345,7 +513,7 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
         if (!(flag & (BF_BOUNDARY | BF_NSKIP))) {
             gather_interior<Lt, ST>(interior_lane<typename ST::T>(tab, i, j, k), g);
             R uu;
-            bgk_relax<Lt, R>(g, om, drho, ux, uy, uz, uu);
+            relax<Lt, R, COLL>(g, om, sh, drho, ux, uy, uz, uu);
             const int Bu = __builtin_amdgcn_readfirstlane(B);
 #pragma unroll
             for (int p = 0; p < Q; p++) store_g<Lt, ST, NTS>(dst, mslot<Lt>(Bu, p, l), p, g[p]);
@@ -354,7 +522,7 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
     }
     gather_cell<Lt, ST>(m, link, B, h, l, src, g);
     R uu;
-    bgk_relax<Lt, R>(g, om, drho, ux, uy, uz, uu);
+    relax<Lt, R, COLL>(g, om, sh, drho, ux, uy, uz, uu);
 
 #pragma unroll
     for (int q = 0; q < Q; q++) {
@@ -404,10 +572,12 @@ constexpr int collide_threads() { return 256; }
 template <int Q, int S>
 constexpr int collide_blocks_per_wg() { return collide_threads<S>() / Lat<Q>::MB; }
 
-template <int Q, int S, bool NTS>
+// COLL: 0 = BGK, 1 / 2 = moment-space collision (D3Q27) on the vector ALU /
+// with the matrix-core transforms; s_high = its rate above second order
+template <int Q, int S, bool NTS, int COLL = 0>
 __global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
     const int32_t *__restrict__ list, int n, DevMesh m, const typename Store<S>::T *__restrict__ src,
-    typename Store<S>::T *__restrict__ dst, double omega_d, BCParams bc) {
+    typename Store<S>::T *__restrict__ dst, double omega_d, BCParams bc, double s_high) {
     using Lt = Lat<Q>;
     using R = typename Store<S>::R;
     constexpr int MB = Lt::MB, BPW = collide_blocks_per_wg<Q, S>();
@@ -423,7 +593,8 @@ __global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
         __syncthreads();
     }
     const int s = threadIdx.x / MB;
-    collide_block<Q, S, BPW, NTS>(m, st, s, threadIdx.x % MB, src, dst, R(omega_d), bc, tab[Lt::D == 3 ? s : 0]);
+    collide_block<Q, S, BPW, NTS, COLL>(m, st, s, threadIdx.x % MB, src, dst, R(omega_d), bc, tab[Lt::D == 3 ? s : 0],
+                                        R(s_high));
 }
 
 // Batched form: level L of every simulation of a batch in one persistent
@@ -1474,10 +1645,25 @@ static void collide_stream_nts(const Ctx &c, const int32_t *list, int n, int L, 
     const int grid = (n + bpw - 1) / bpw;
     const T *src = (const T *)c.f[sp];
     T *dst = (T *)c.f[1 - sp];
-    if ((int64_t)n * Q * c.mb * (int64_t)sizeof(T) > c.stream_bytes)
-        k_collide_stream<Q, S, true><<<grid, collide_threads<S>(), 0, c.stream>>>(list, n, c.m, src, dst, lp.omega[L], bc);
-    else
-        k_collide_stream<Q, S, false><<<grid, collide_threads<S>(), 0, c.stream>>>(list, n, c.m, src, dst, lp.omega[L], bc);
+    const bool nts = (int64_t)n * Q * c.mb * (int64_t)sizeof(T) > c.stream_bytes;
+    const int tpb = collide_threads<S>();
+    const double om = lp.omega[L];
+    if constexpr (Q == 27) {
+        if (c.coll == AMR_COLLIDE_MRT) {
+            if (nts) k_collide_stream<Q, S, true, 1><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, c.s_high);
+            else k_collide_stream<Q, S, false, 1><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, c.s_high);
+            return;
+        }
+        if constexpr (S != AMR_F64) {
+            if (c.coll == AMR_COLLIDE_MRT_MFMA) {
+                if (nts) k_collide_stream<Q, S, true, 2><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, c.s_high);
+                else k_collide_stream<Q, S, false, 2><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, c.s_high);
+                return;
+            }
+        }
+    }
+    if (nts) k_collide_stream<Q, S, true><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, om);
+    else k_collide_stream<Q, S, false><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, om);
 }
 
 void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, const BCParams &bc) {

@@ -347,6 +347,8 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
     c.staging = a + lay.staging;
     c.staging_bytes = lay.staging_bytes;
     c.stream_bytes = kStreamingBytes;
+    c.coll = AMR_COLLIDE_BGK;
+    c.s_high = 1.0;
     c.stream = (hipStream_t)hip_stream;
     std::vector<int32_t> slist;
     for (int B = 0; B < (int)h->solid.size(); B++)
@@ -590,6 +592,30 @@ amr_status amr_adapt(amr_t *h, amr_adapt_stats *stats) {
         stats->n_free = dc.gtop;
         for (int L = 0; L < h->lmax; L++) stats->level_blocks[L] = h->nids[L];
         for (int k = 0; k < AMR_T_STEPS; k++) stats->step_ms[k] = h->step_ms[k];
+    }
+    return AMR_OK;
+}
+
+amr_status amr_set_collision(amr_t *h, int32_t kind, double s_high) {
+    if (!h) return fail(AMR_ERR_ARG, "handle is NULL");
+    if (kind == AMR_COLLIDE_BGK) {
+        if (h->c.coll != AMR_COLLIDE_BGK) {
+            h->c.coll = AMR_COLLIDE_BGK;
+            drop_graphs(h);
+        }
+        return AMR_OK;
+    }
+    if (kind != AMR_COLLIDE_MRT && kind != AMR_COLLIDE_MRT_MFMA)
+        return fail(AMR_ERR_ARG, "unknown collision kind %d", kind);
+    if (h->c.q != 27) return fail(AMR_ERR_ARG, "the moment-space collision is implemented for D3Q27 only");
+    if (kind == AMR_COLLIDE_MRT_MFMA && h->c.storage == AMR_F64)
+        return fail(AMR_ERR_ARG, "AMR_COLLIDE_MRT_MFMA needs a storage with FP32 arithmetic");
+    if (!(s_high > 0.0 && s_high < 2.0)) return fail(AMR_ERR_ARG, "s_high must lie in (0, 2), not %g", s_high);
+    if (h->batches > 0) return fail(AMR_ERR_ARG, "the handle is in a batch, which advances BGK members only");
+    if (kind != h->c.coll || s_high != h->c.s_high) {
+        h->c.coll = kind;
+        h->c.s_high = s_high;
+        drop_graphs(h);  // captured steps hold the collide kernels and the rate
     }
     return AMR_OK;
 }

@@ -1,0 +1,108 @@
+"""The optional moment-space collision (D3Q27) on the GPU, through the C ABI.
+
+The paper's method is BGK; it names moment-space collision as the
+alternative (Sec. "Lattice Boltzmann Method").  Checked: at s_high = omega both
+forms (vector ALU, matrix cores) give the BGK fields bit for bit; with other
+rates the vector-ALU form follows the oracle's moment-space collision per cell
+(FP64 storage 1e-12, FP32 1e-5), and the matrix-core form (FP16 operands of the
+high-moment transforms) stays within the bound derived in its test."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_08085_amd import abi, workloads as W
+from parity_util import Pair, assert_cells, field_errors, velocity_scale
+
+pytestmark = pytest.mark.gpu
+
+
+def cavity(storage, lmax=2):
+    return W.cavity(3, 27, 16, lmax, 100.0, storage=storage, seed=21, cap=1200)
+
+
+def run_gpu(case, kind, s_high, steps=12, refine=True):
+    g = abi.AmrLbm(case)
+    g.set_root_rho_u(case.initial_rho_u())
+    if kind != abi.COLLIDE_BGK:
+        g.set_collision(kind, s_high)
+    if refine and case.lmax > 1:
+        tags = np.zeros(case.cap, np.int8)
+        tags[[0, 5, 21, 42]] = 1
+        g.tag(tags_in=tags)
+        g.adapt()
+    g.step(steps, graph=True)
+    f = g.get_block_f_all()
+    g.close()
+    return f
+
+
+@pytest.mark.parametrize("storage,kind,tol", [("f64", abi.COLLIDE_MRT, 1e-14), ("f32s", abi.COLLIDE_MRT, 1e-6),
+                                              ("f32s", abi.COLLIDE_MRT_MFMA, 1e-6),
+                                              ("f16s", abi.COLLIDE_MRT_MFMA, 2 ** -10)])
+def test_equal_rates_reproduce_bgk(storage, kind, tol):
+    """s_high = omega: the high-moment correction is (s_high - omega) times a
+    finite sum, so only the rounding of omega (the library derives it from the
+    viscosity its own way) separates the two runs: per population within tol
+    of |f| (FP64 1e-14, FP32 1e-6; 16-bit storage one FP16 ulp, 2^-10 relative,
+    where a last-bit difference tips a rounding)"""
+    case = cavity(storage, lmax=1)
+    om = 1.0 / (0.5 + 3.0 * case.nu0)
+    a = run_gpu(case, abi.COLLIDE_BGK, 1.0, refine=False)
+    b = run_gpu(case, kind, om, refine=False)
+    rel = np.abs(a - b) / np.maximum(np.abs(a), 1e-300)
+    print("%s kind %d: max relative difference from BGK %.3g, cells differing %d of %d"
+          % (storage, kind, rel.max(), int((a != b).sum()), a.size))
+    assert rel.max() <= tol
+
+
+def pair_run(storage, kind, s_high, steps=12):
+    case = cavity(storage)
+    p = Pair(case)
+    p.o.set_collision(1, s_high)
+    p.g.set_collision(kind, s_high)
+    tags = np.zeros(case.cap, np.int8)
+    tags[[0, 5, 21, 42]] = 1
+    p.tag_replay(tags)
+    p.adapt()
+    p.check_mesh("refined")
+    p.step(steps, graph=True)
+    return p
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32s", 1e-5)])
+def test_vector_alu_form_matches_the_oracle(storage, tol):
+    p = pair_run(storage, abi.COLLIDE_MRT, 1.2)
+    p.assert_parity(tol, "moment-space collision, vector ALU, %s" % storage)
+
+
+def test_matrix_core_form_error_is_bounded():
+    """FP32 storage, high-moment transforms with FP16 operands.  Each sweep
+    rounds the scaled non-equilibrium parts n and the scaled high moments to
+    FP16 (relative 2^-11 each) before a correction of size |s_high - omega| |n|
+    per population (coefficients of the transform pair summing to at most 1 in
+    the relaxed direction).  With |n| up to ~0.15 |f| at the lid corners and
+    |s_high - omega| < 0.7 here, one sweep errs by up to ~2 x 2^-11 x 0.7 x 0.15
+    = 1e-4 of |f|, and the relaxation damps earlier sweeps' errors.  Bar per
+    population: 2e-4 of |f| (rho and u at the FP32 bar); measured 6.8e-5."""
+    p = pair_run("f32s", abi.COLLIDE_MRT_MFMA, 1.2)
+    e = p.errors()
+    print("moment-space collision, matrix cores, f32s:", {k: v for k, v in e.items() if isinstance(v, float)})
+    assert e["f_cell"] < 2e-4 and e["block_f_cell"] < 2e-4, e
+    assert e["rho_cell"] < 1e-5 and e["u_cell"] < 1e-5 / (3 * velocity_scale(p.case)), e
+
+
+def test_rejected_configurations():
+    with pytest.raises(abi.AmrError):
+        g = abi.AmrLbm(W.cavity(3, 19, 8, 1, 100.0, storage="f32s", cap=8))
+        try:
+            g.set_collision(abi.COLLIDE_MRT, 1.2)
+        finally:
+            g.close()
+    g = abi.AmrLbm(W.cavity(3, 27, 8, 1, 100.0, storage="f64", cap=8))
+    try:
+        with pytest.raises(abi.AmrError):
+            g.set_collision(abi.COLLIDE_MRT_MFMA, 1.2)
+        with pytest.raises(abi.AmrError):
+            g.set_collision(abi.COLLIDE_MRT, 2.5)
+    finally:
+        g.close()
