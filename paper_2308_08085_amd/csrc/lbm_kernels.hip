@@ -1277,6 +1277,20 @@ __global__ __launch_bounds__(256) void k_velocity(const int32_t *__restrict__ li
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
     const int B = st.id[s];
     if (B < 0) return;
+    // The criterion reads velocities of leaf blocks and, across the six faces
+    // of a leaf, of its same-level neighbours: a refined block none of whose
+    // face neighbours is a leaf is never read.
+    if (is_refined(m.status[B])) {
+        bool read = false;
+#pragma unroll
+        for (int a = 0; a < Lt::D; a++)
+            for (int sg = -1; sg <= 1; sg += 2) {
+                const int32_t code = st.link[s][region_of<Lt>(a == 0 ? 1 + 3 * sg : 1, a == 1 ? 1 + 3 * sg : 1,
+                                                              a == 2 ? 1 + 3 * sg : 1)];
+                if (code >= 0 && code < m.cap && m.status[code] == ST_UNREF) read = true;
+            }
+        if (!read) return;
+    }
     double fv[Q];
     bool done = false;
     if constexpr (Lt::D == 3) {
