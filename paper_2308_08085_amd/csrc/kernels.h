@@ -78,6 +78,10 @@ void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &
 void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const LevelParams &lp);
 // mode 0: interface parent cells; 1: every parent cell (non-refined entries are skipped)
 void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells);
+// ghost interpolation into level L+1 (interface parents ilist) and the
+// collide-stream sweep of level L (launch order clist) in one launch; 3-D, BGK
+void launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
+                           const LevelParams &lp, const BCParams &bc);
 void launch_fill_rest(const Ctx &c);
 // initial condition on root blocks [b0, b1) from rho_u_dev[((B - b0) Mb + l) 4]
 void launch_set_rho_u_root(const Ctx &c, const double *rho_u_dev, int b0, int b1);

@@ -574,16 +574,17 @@ constexpr int collide_blocks_per_wg() { return collide_threads<S>() / Lat<Q>::MB
 
 // COLL: 0 = BGK, 1 / 2 = moment-space collision (D3Q27) on the vector ALU /
 // with the matrix-core transforms; s_high = its rate above second order
-template <int Q, int S, bool NTS, int COLL = 0>
-__global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
-    const int32_t *__restrict__ list, int n, DevMesh m, const typename Store<S>::T *__restrict__ src,
-    typename Store<S>::T *__restrict__ dst, double omega_d, BCParams bc, double s_high) {
+// One workgroup's share of a level sweep: blocks wg * BPW .. of the list
+template <int Q, int S, bool NTS, int COLL>
+__device__ __forceinline__ void collide_wg(const int32_t *__restrict__ list, int n, const DevMesh &m,
+                                           const typename Store<S>::T *__restrict__ src,
+                                           typename Store<S>::T *__restrict__ dst, double omega_d, const BCParams &bc,
+                                           double s_high, int wg) {
     using Lt = Lat<Q>;
     using R = typename Store<S>::R;
     constexpr int MB = Lt::MB, BPW = collide_blocks_per_wg<Q, S>();
     __shared__ BlockStage<Lt, BPW> st;
     __shared__ uint64_t tab[Lt::D == 3 ? BPW : 1][27];
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int base = wg * BPW;
     if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
     __syncthreads();
@@ -595,6 +596,13 @@ __global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
     const int s = threadIdx.x / MB;
     collide_block<Q, S, BPW, NTS, COLL>(m, st, s, threadIdx.x % MB, src, dst, R(omega_d), bc, tab[Lt::D == 3 ? s : 0],
                                         R(s_high));
+}
+
+template <int Q, int S, bool NTS, int COLL = 0>
+__global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
+    const int32_t *__restrict__ list, int n, DevMesh m, const typename Store<S>::T *__restrict__ src,
+    typename Store<S>::T *__restrict__ dst, double omega_d, BCParams bc, double s_high) {
+    collide_wg<Q, S, NTS, COLL>(list, n, m, src, dst, omega_d, bc, s_high, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Batched form: level L of every simulation of a batch in one persistent
@@ -779,17 +787,45 @@ __device__ inline bool interp_target(const DevMesh &m, int P, int nc) {
 }
 
 template <int Q, int S, int CUB>
-__global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list, int n, DevMesh m,
-                                                typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
-                                                int all_cells) {
+__device__ __forceinline__ void interp_wg(const int32_t *__restrict__ list, int n, const DevMesh &m,
+                                          typename Store<S>::T *f0, typename Store<S>::T *f1, const LevelParams &lp,
+                                          int all_cells, int item) {
     using R = typename Store<S>::R;
     __shared__ InterpSmem<Lat<Q>, R> sm;
-    if ((int)blockIdx.x >= n) return;
-    const int P = list[blockIdx.x];
+    if (item >= n) return;
+    const int P = list[item];
     if (!interp_target(m, P, Lat<Q>::NC)) return;
     const int L = m.level[P];
     interp_parent<Q, S, CUB>(m, P, lp.par[L] ? f1 : f0, lp.par[L + 1] ? f1 : f0, R(lp.r_cf[L]), all_cells, sm,
                              threadIdx.x);
+}
+
+template <int Q, int S, int CUB>
+__global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list, int n, DevMesh m,
+                                                typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
+                                                int all_cells) {
+    interp_wg<Q, S, CUB>(list, n, m, f0, f1, lp, all_cells, blockIdx.x);
+}
+
+// The ghost interpolation into level L+1 and the collide-stream sweep of level
+// L in one launch (3-D): workgroups 0 .. ni-1 interpolate one parent each, the
+// rest sweep the level.  Both read level L's current buffer; one writes ghost
+// cells of level L+1, the other level L's other buffer, so they need no
+// order, and small levels save a launch gap.
+template <int Q, int S, bool NTS, int CUB>
+__global__ __launch_bounds__(256) void k_interp_collide(const int32_t *__restrict__ ilist, int ni,
+                                                        const int32_t *__restrict__ clist, int nblk, DevMesh m,
+                                                        typename Store<S>::T *f0, typename Store<S>::T *f1,
+                                                        LevelParams lp, int L, BCParams bc) {
+    const int b = blockIdx.x;
+    if (b < ni) {
+        interp_wg<Q, S, CUB>(ilist, ni, m, f0, f1, lp, 0, b);
+    } else {
+        const typename Store<S>::T *src = lp.par[L] ? f1 : f0;
+        typename Store<S>::T *dst = lp.par[L] ? f0 : f1;
+        collide_wg<Q, S, NTS, 0>(clist, nblk, m, src, dst, lp.omega[L], bc, lp.omega[L],
+                                 xcd_remap(b - ni, (int)gridDim.x - ni));
+    }
 }
 
 // Batched ghost fill of level L+1 from level L (interface parents of every
@@ -1686,6 +1722,33 @@ static void collide_stream_nts(const Ctx &c, const int32_t *list, int n, int L, 
 void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, const BCParams &bc) {
     if (n <= 0) return;
     AMR_DISPATCH(c.q, c.storage, (collide_stream_nts<Qc, Sc>(c, list, n, L, lp, bc)));
+}
+
+template <int Q, int S>
+static void interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
+                           const LevelParams &lp, const BCParams &bc) {
+    using T = typename Store<S>::T;
+    constexpr int bpw = collide_blocks_per_wg<Q, S>();
+    const int grid = ni + (nblk + bpw - 1) / bpw;
+    const bool nts = (int64_t)nblk * Q * c.mb * (int64_t)sizeof(T) > c.stream_bytes;
+    T *f0 = (T *)c.f[0], *f1 = (T *)c.f[1];
+    if (c.m.interp == AMR_INTERP_CUBIC) {
+        if (nts) k_interp_collide<Q, S, true, 1><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
+        else k_interp_collide<Q, S, false, 1><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
+    } else {
+        if (nts) k_interp_collide<Q, S, true, 0><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
+        else k_interp_collide<Q, S, false, 0><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
+    }
+}
+
+void launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
+                           const LevelParams &lp, const BCParams &bc) {
+    if (c.dim != 3) return;
+    if (c.q == 19) {
+        AMR_DISPATCH(19, c.storage, (interp_collide<19, Sc>(c, ilist, ni, clist, nblk, L, lp, bc)));
+    } else {
+        AMR_DISPATCH(27, c.storage, (interp_collide<27, Sc>(c, ilist, ni, clist, nblk, L, lp, bc)));
+    }
 }
 
 void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {
