@@ -72,6 +72,10 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("HIP library %s is missing: run paper_2308_08085_amd.build.build()" % LIB_PATH)
+        # torch first: the library must bind to the HIP runtime torch already
+        # loaded (the arenas are torch allocations); loaded the other way round
+        # a process can end up with two runtimes and no shared device pointers
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.amr_query_bytes.argtypes = [C.POINTER(Config), C.POINTER(C.c_uint64)]

@@ -79,7 +79,7 @@ void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const L
 // mode 0: interface parent cells; 1: every parent cell (non-refined entries are skipped)
 void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells);
 // ghost interpolation into level L+1 (interface parents ilist) and the
-// collide-stream sweep of level L (launch order clist) in one launch; 3-D, BGK
+// collide-stream sweep of level L (launch order clist) in one launch; BGK
 void launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
                            const LevelParams &lp, const BCParams &bc);
 void launch_fill_rest(const Ctx &c);

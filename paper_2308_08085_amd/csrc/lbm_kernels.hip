@@ -808,10 +808,11 @@ __global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list
 }
 
 // The ghost interpolation into level L+1 and the collide-stream sweep of level
-// L in one launch (3-D): workgroups 0 .. ni-1 interpolate one parent each, the
-// rest sweep the level.  Both read level L's current buffer; one writes ghost
-// cells of level L+1, the other level L's other buffer, so they need no
-// order, and small levels save a launch gap.
+// L in one 256-thread launch: workgroups 0 .. ni-1 interpolate one parent each
+// (in 2-D with the first 64 threads; interp_parent strides by the workgroup
+// size), the rest sweep the level.  Both read level L's current buffer; one
+// writes ghost cells of level L+1, the other level L's other buffer, so they
+// need no order, and small levels save a launch gap.
 template <int Q, int S, bool NTS, int CUB>
 __global__ __launch_bounds__(256) void k_interp_collide(const int32_t *__restrict__ ilist, int ni,
                                                         const int32_t *__restrict__ clist, int nblk, DevMesh m,
@@ -1743,12 +1744,7 @@ static void interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int
 
 void launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
                            const LevelParams &lp, const BCParams &bc) {
-    if (c.dim != 3) return;
-    if (c.q == 19) {
-        AMR_DISPATCH(19, c.storage, (interp_collide<19, Sc>(c, ilist, ni, clist, nblk, L, lp, bc)));
-    } else {
-        AMR_DISPATCH(27, c.storage, (interp_collide<27, Sc>(c, ilist, ni, clist, nblk, L, lp, bc)));
-    }
+    AMR_DISPATCH(c.q, c.storage, (interp_collide<Qc, Sc>(c, ilist, ni, clist, nblk, L, lp, bc)));
 }
 
 void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {

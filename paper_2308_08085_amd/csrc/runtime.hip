@@ -186,13 +186,12 @@ void step_level(amr_handle *h, int L) {
         return;
     }
     const size_t cap = (size_t)h->c.m.cap;
-    // Small 3-D BGK levels outside profiled runs take the ghost interpolation
-    // into the same launch: one launch gap (~10 us) fewer per level visit.
-    // Large levels keep two launches: the fused kernel needs more registers
-    // (99 VGPRs at 16-bit storage against 68) and their launches are long.
-    constexpr int kFuseMaxBlocks = 16384;
-    const bool fuse = h->niface[L] > 0 && h->nids[L] <= kFuseMaxBlocks && h->c.dim == 3 &&
-                      h->c.coll == AMR_COLLIDE_BGK && !h->profiling;
+    // Small BGK levels outside profiled runs take the ghost interpolation into
+    // the same launch: one launch gap (~10 us) fewer per level visit.  Large
+    // levels keep two launches: the fused kernel needs more registers (99 VGPRs
+    // for D3Q27 at 16-bit storage against 68) and their launches are long.
+    const int fuse_max = h->c.dim == 3 ? 16384 : 65536;  // blocks of 64 / 16 cells
+    const bool fuse = h->niface[L] > 0 && h->nids[L] <= fuse_max && h->c.coll == AMR_COLLIDE_BGK && !h->profiling;
     if (fuse) {
         const LevelParams lp = level_params(h);
         launch_interp_collide(h->c, h->c.iface + L * cap, h->niface[L], h->c.order + L * cap, h->nids[L], L, lp, h->bc);
