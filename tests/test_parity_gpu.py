@@ -394,3 +394,24 @@ def test_stream_bytes_knob():
         g.adapt()
         g.step(5, graph=True)
     assert np.array_equal(a.get_block_f_all(), b.get_block_f_all())
+
+
+@pytest.mark.parametrize("dim,q,storage", [(3, 19, "f32s"), (3, 27, "f16s"), (2, 9, "f64")])
+def test_joined_launches_equal_separate_launches(dim, q, storage):
+    """small levels join the ghost interpolation into level L+1 and the sweep of
+    level L in one launch (replayed and eager steps); profiled steps launch
+    them separately.  Both give the same fields bit for bit, across adaptation"""
+    case = _cav(dim, q, lmax=3, storage=storage)
+    out = []
+    for profile in (True, False):
+        g = abi.AmrLbm(case)
+        g.set_root_rho_u(case.initial_rho_u())
+        for _ in range(2):
+            g.step(10, graph=not profile, profile=profile)
+            g.tag(abi.TAG_VORTICITY_REL, theta=0.1)
+            g.adapt()
+        g.step(6, graph=not profile, profile=profile)
+        assert g.counts()[1] > 0
+        out.append(g.get_block_f_all())
+        g.close()
+    assert np.array_equal(out[0], out[1])
