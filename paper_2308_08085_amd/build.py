@@ -20,6 +20,10 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fuse only within one source expression: every kernel that
+    # shares an arithmetic routine (the plain, joined and batched sweeps, and
+    # their variants) then rounds it the same way, whatever code surrounds it
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -69,8 +69,10 @@ struct Ctx {
 constexpr int64_t kStreamingBytes = int64_t(128) << 20;
 
 // ---- LBM kernels (lbm_kernels.hip) ----
-void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp,
-                           const BCParams &bc);
+// exchange: also add the momentum exchange with solid blocks (BGK sweeps with
+// ordinary stores); returns whether it did, else launch_exchange follows
+bool launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp,
+                           const BCParams &bc, bool exchange = false);
 // mode 0: ghost cells of children with an N_SKIP link; 1: every cell of every child
 void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells);
 // after new children (parents in `list`) were interpolated: the populations of
@@ -79,9 +81,10 @@ void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const L
 // mode 0: interface parent cells; 1: every parent cell (non-refined entries are skipped)
 void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells);
 // ghost interpolation into level L+1 (interface parents ilist) and the
-// collide-stream sweep of level L (launch order clist) in one launch; BGK
-void launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
-                           const LevelParams &lp, const BCParams &bc);
+// collide-stream sweep of level L (launch order clist) in one launch; BGK;
+// exchange and the result as for launch_collide_stream
+bool launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
+                           const LevelParams &lp, const BCParams &bc, bool exchange = false);
 void launch_fill_rest(const Ctx &c);
 // initial condition on root blocks [b0, b1) from rho_u_dev[((B - b0) Mb + l) 4]
 void launch_set_rho_u_root(const Ctx &c, const double *rho_u_dev, int b0, int b1);

@@ -51,13 +51,25 @@ __device__ inline void moments_g(const R *g, R &drho, R &ux, R &uy, R &uz) {
     uz = jz / rho;
 }
 
-// deviation of the second-order equilibrium from the rest state, w (rho - 1) +
-// w rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+// a b + c, rounded once
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// deviation of the second-order equilibrium from the rest state over the
+// weight: (rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u), so g_eq = w y.
+// Callers fuse the weight into the difference with g (one rounding fewer).
 template <typename Lt, typename R>
-__device__ inline R geq(int p, R drho, R ux, R uy, R uz, R uu) {
+__device__ inline R geq_y(int p, R drho, R ux, R uy, R uz, R uu) {
     const R cu = R(Lt::cx(p)) * ux + R(Lt::cy(p)) * uy + R(Lt::cz(p)) * uz;
     const R rho = R(1) + drho;
-    return R(Lt::w(p)) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+    return drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+}
+
+// g_eq + r (g - g_eq): the non-equilibrium part rescaled by r
+template <typename Lt, typename R>
+__device__ __forceinline__ R rescale_neq(int p, R g, R r, R drho, R ux, R uy, R uz, R uu) {
+    const R w = R(Lt::w(p)), y = geq_y<Lt, R>(p, drho, ux, uy, uz, uu);
+    return fmadd(w, y, r * fmadd(-w, y, g));
 }
 
 template <typename Lt, typename ST>
@@ -192,7 +204,8 @@ __device__ __forceinline__ void bgk_relax(R *g, R om, R &drho, R &ux, R &uy, R &
     moments_g<Lt, R>(g, drho, ux, uy, uz);
     uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
-    for (int p = 0; p < Lt::Q; p++) g[p] += om * (geq<Lt, R>(p, drho, ux, uy, uz, uu) - g[p]);
+    for (int p = 0; p < Lt::Q; p++)
+        g[p] = fmadd(om, fmadd(R(Lt::w(p)), geq_y<Lt, R>(p, drho, ux, uy, uz, uu), -g[p]), g[p]);
 }
 
 // ---------------------------------------------------------------------------
@@ -352,7 +365,7 @@ __device__ __forceinline__ void relax(R *g, R om, R sh, R &drho, R &ux, R &uy, R
         R n[27];
 #pragma unroll
         for (int p = 0; p < 27; p++) {
-            n[p] = g[p] - geq<Lt, R>(p, drho, ux, uy, uz, uu);
+            n[p] = fmadd(-R(Lt::w(p)), geq_y<Lt, R>(p, drho, ux, uy, uz, uu), g[p]);
             g[p] -= om * n[p];
         }
         if constexpr (COLL == 1)
@@ -488,8 +501,11 @@ __device__ inline void decode_item(uint32_t it, int &sim, int &B) {
 // from a region covered only by a coarser block keeps the cell's own
 // post-collision value (halo record).  NTS: write with non-temporal stores
 // (for levels whose output is too large to stay cached until the next sweep).
+// EX: a leaf block next to a solid also adds its momentum exchange of this
+// sweep to its total, exactly as the separate pass (exchange_block) would from
+// the values just stored.
 // Body: the cells of staged block s (this thread: cell l).
-template <int Q, int S, int NBLK, bool NTS, int COLL = 0>
+template <int Q, int S, int NBLK, bool NTS, int COLL = 0, bool EX = false>
 __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage<Lat<Q>, NBLK> &st, int s, int l,
                                               const typename Store<S>::T *__restrict__ src,
                                               typename Store<S>::T *__restrict__ dst, typename Store<S>::R om,
@@ -524,6 +540,7 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
     R uu;
     relax<Lt, R, COLL>(g, om, sh, drho, ux, uy, uz, uu);
 
+    [[maybe_unused]] double fx = 0.0, fy = 0.0, fz = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         if (flag & BF_BOUNDARY) {
@@ -532,6 +549,15 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
                 R val;
                 if (code == kSolid) {
                     val = g[q];
+                    if constexpr (EX) {
+                        // 2 f*_q c_q from the value as stored (rounded to the storage type)
+                        typename ST::T t;
+                        ST::st(&t, ST::shift ? val : val + R(Lt::w(q)));
+                        const double two_f = 2.0 * double(ST::ld(&t) + (ST::shift ? Lt::w(q) : 0.0));
+                        fx += two_f * Lt::cx(q);
+                        fy += two_f * Lt::cy(q);
+                        fz += two_f * Lt::cz(q);
+                    }
                 } else {
                     const int face = -3 - code;
                     const R cx = R(Lt::cx(q)), cy = R(Lt::cy(q)), cz = R(Lt::cz(q));
@@ -549,6 +575,22 @@ __device__ __forceinline__ void collide_block(const DevMesh &m, const BlockStage
             }
         }
         store_g<Lt, ST, NTS>(dst, mslot<Lt>(B, q, l), q, g[q]);
+    }
+    if constexpr (EX) {
+        // uniform over the block's lanes: sum over the block, one lane adds
+        if ((flag & BF_SOLID) && m.status[B] == ST_UNREF) {
+#pragma unroll
+            for (int mask = 1; mask < Lt::MB; mask <<= 1) {
+                fx += __shfl_xor(fx, mask, 64);
+                fy += __shfl_xor(fy, mask, 64);
+                fz += __shfl_xor(fz, mask, 64);
+            }
+            if (l == 0) {
+                m.force[(int64_t)B * 3 + 0] += fx;
+                m.force[(int64_t)B * 3 + 1] += fy;
+                m.force[(int64_t)B * 3 + 2] += fz;
+            }
+        }
     }
     if ((flag & BF_NSKIP) && h >= 0) {
 #pragma unroll
@@ -575,7 +617,7 @@ constexpr int collide_blocks_per_wg() { return collide_threads<S>() / Lat<Q>::MB
 // COLL: 0 = BGK, 1 / 2 = moment-space collision (D3Q27) on the vector ALU /
 // with the matrix-core transforms; s_high = its rate above second order
 // One workgroup's share of a level sweep: blocks wg * BPW .. of the list
-template <int Q, int S, bool NTS, int COLL>
+template <int Q, int S, bool NTS, int COLL, bool EX = false>
 __device__ __forceinline__ void collide_wg(const int32_t *__restrict__ list, int n, const DevMesh &m,
                                            const typename Store<S>::T *__restrict__ src,
                                            typename Store<S>::T *__restrict__ dst, double omega_d, const BCParams &bc,
@@ -594,15 +636,15 @@ __device__ __forceinline__ void collide_wg(const int32_t *__restrict__ list, int
         __syncthreads();
     }
     const int s = threadIdx.x / MB;
-    collide_block<Q, S, BPW, NTS, COLL>(m, st, s, threadIdx.x % MB, src, dst, R(omega_d), bc, tab[Lt::D == 3 ? s : 0],
-                                        R(s_high));
+    collide_block<Q, S, BPW, NTS, COLL, EX>(m, st, s, threadIdx.x % MB, src, dst, R(omega_d), bc,
+                                            tab[Lt::D == 3 ? s : 0], R(s_high));
 }
 
-template <int Q, int S, bool NTS, int COLL = 0>
+template <int Q, int S, bool NTS, int COLL = 0, bool EX = false>
 __global__ __launch_bounds__(collide_threads<S>()) void k_collide_stream(
     const int32_t *__restrict__ list, int n, DevMesh m, const typename Store<S>::T *__restrict__ src,
     typename Store<S>::T *__restrict__ dst, double omega_d, BCParams bc, double s_high) {
-    collide_wg<Q, S, NTS, COLL>(list, n, m, src, dst, omega_d, bc, s_high, xcd_remap(blockIdx.x, gridDim.x));
+    collide_wg<Q, S, NTS, COLL, EX>(list, n, m, src, dst, omega_d, bc, s_high, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Batched form: level L of every simulation of a batch in one persistent
@@ -751,10 +793,7 @@ __device__ __forceinline__ void interp_parent(const DevMesh &m, int P, const typ
         moments_g<Lt, R>(g, drho, ux, uy, uz);
         const R uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
-        for (int p = 0; p < Q; p++) {
-            const R ge = geq<Lt, R>(p, drho, ux, uy, uz, uu);
-            sm.g[p][t] = ge + r * (g[p] - ge);
-        }
+        for (int p = 0; p < Q; p++) sm.g[p][t] = rescale_neq<Lt, R>(p, g[p], r, drho, ux, uy, uz, uu);
     }
     __syncthreads();
     const int cubic = CUB == 2 ? m.interp : CUB;
@@ -812,8 +851,9 @@ __global__ __launch_bounds__(256) void k_interp(const int32_t *__restrict__ list
 // (in 2-D with the first 64 threads; interp_parent strides by the workgroup
 // size), the rest sweep the level.  Both read level L's current buffer; one
 // writes ghost cells of level L+1, the other level L's other buffer, so they
-// need no order, and small levels save a launch gap.
-template <int Q, int S, bool NTS, int CUB>
+// need no order, and small levels save a launch gap.  EX: the sweep adds the
+// momentum exchange too (collide_block).
+template <int Q, int S, bool NTS, int CUB, bool EX = false>
 __global__ __launch_bounds__(256) void k_interp_collide(const int32_t *__restrict__ ilist, int ni,
                                                         const int32_t *__restrict__ clist, int nblk, DevMesh m,
                                                         typename Store<S>::T *f0, typename Store<S>::T *f1,
@@ -824,8 +864,8 @@ __global__ __launch_bounds__(256) void k_interp_collide(const int32_t *__restric
     } else {
         const typename Store<S>::T *src = lp.par[L] ? f1 : f0;
         typename Store<S>::T *dst = lp.par[L] ? f0 : f1;
-        collide_wg<Q, S, NTS, 0>(clist, nblk, m, src, dst, lp.omega[L], bc, lp.omega[L],
-                                 xcd_remap(b - ni, (int)gridDim.x - ni));
+        collide_wg<Q, S, NTS, 0, EX>(clist, nblk, m, src, dst, lp.omega[L], bc, lp.omega[L],
+                                     xcd_remap(b - ni, (int)gridDim.x - ni));
     }
 }
 
@@ -911,10 +951,7 @@ __global__ __launch_bounds__(256) void k_refresh_neighbours(const int32_t *__res
                 moments_g<Lt, R>(g, drho, ux, uy, uz);
                 const R uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
-                for (int p = 0; p < Q; p++) {
-                    const R ge = geq<Lt, R>(p, drho, ux, uy, uz, uu);
-                    s_g[p][t] = ge + r * (g[p] - ge);
-                }
+                for (int p = 0; p < Q; p++) s_g[p][t] = rescale_neq<Lt, R>(p, g[p], r, drho, ux, uy, uz, uu);
             }
             __syncthreads();
             if (t < MB) {
@@ -1016,8 +1053,7 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, 
     const R uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
     for (int p = 0; p < Q; p++) {
-        const R ge = geq<Lt, R>(p, drho, ux, uy, uz, uu);
-        R v = ge + r * (g[p] - ge);
+        R v = rescale_neq<Lt, R>(p, g[p], r, drho, ux, uy, uz, uu);
         v = xor_sum(v, 1);
         v = xor_sum(v, 4);
         if (Lt::D == 3) v = xor_sum(v, 16);
@@ -1691,8 +1727,8 @@ static inline int grid_blocks(int64_t nblocks, int mb) {
 // Infinity Cache) stores with non-temporal writes.  Smaller levels are still
 // cached when the next sweep (or the interpolation and averaging) reads them.
 template <int Q, int S>
-static void collide_stream_nts(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp,
-                               const BCParams &bc) {
+static bool collide_stream_nts(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp,
+                               const BCParams &bc, bool exchange) {
     using T = typename Store<S>::T;
     const int sp = lp.par[L];
     constexpr int bpw = collide_blocks_per_wg<Q, S>();
@@ -1706,33 +1742,48 @@ static void collide_stream_nts(const Ctx &c, const int32_t *list, int n, int L, 
         if (c.coll == AMR_COLLIDE_MRT) {
             if (nts) k_collide_stream<Q, S, true, 1><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, c.s_high);
             else k_collide_stream<Q, S, false, 1><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, c.s_high);
-            return;
+            return false;
         }
         if constexpr (S != AMR_F64) {
             if (c.coll == AMR_COLLIDE_MRT_MFMA) {
                 if (nts) k_collide_stream<Q, S, true, 2><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, c.s_high);
                 else k_collide_stream<Q, S, false, 2><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, c.s_high);
-                return;
+                return false;
             }
         }
     }
+    if (exchange && !nts) {
+        k_collide_stream<Q, S, false, 0, true><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, om);
+        return true;
+    }
     if (nts) k_collide_stream<Q, S, true><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, om);
     else k_collide_stream<Q, S, false><<<grid, tpb, 0, c.stream>>>(list, n, c.m, src, dst, om, bc, om);
+    return false;
 }
 
-void launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, const BCParams &bc) {
-    if (n <= 0) return;
-    AMR_DISPATCH(c.q, c.storage, (collide_stream_nts<Qc, Sc>(c, list, n, L, lp, bc)));
+bool launch_collide_stream(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, const BCParams &bc,
+                           bool exchange) {
+    if (n <= 0) return false;
+    bool done = false;
+    AMR_DISPATCH(c.q, c.storage, (done = collide_stream_nts<Qc, Sc>(c, list, n, L, lp, bc, exchange)));
+    return done;
 }
 
 template <int Q, int S>
-static void interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
-                           const LevelParams &lp, const BCParams &bc) {
+static bool interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
+                           const LevelParams &lp, const BCParams &bc, bool exchange) {
     using T = typename Store<S>::T;
     constexpr int bpw = collide_blocks_per_wg<Q, S>();
     const int grid = ni + (nblk + bpw - 1) / bpw;
     const bool nts = (int64_t)nblk * Q * c.mb * (int64_t)sizeof(T) > c.stream_bytes;
     T *f0 = (T *)c.f[0], *f1 = (T *)c.f[1];
+    if (exchange && !nts) {
+        if (c.m.interp == AMR_INTERP_CUBIC)
+            k_interp_collide<Q, S, false, 1, true><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
+        else
+            k_interp_collide<Q, S, false, 0, true><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
+        return true;
+    }
     if (c.m.interp == AMR_INTERP_CUBIC) {
         if (nts) k_interp_collide<Q, S, true, 1><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
         else k_interp_collide<Q, S, false, 1><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
@@ -1740,11 +1791,14 @@ static void interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int
         if (nts) k_interp_collide<Q, S, true, 0><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
         else k_interp_collide<Q, S, false, 0><<<grid, 256, 0, c.stream>>>(ilist, ni, clist, nblk, c.m, f0, f1, lp, L, bc);
     }
+    return false;
 }
 
-void launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
-                           const LevelParams &lp, const BCParams &bc) {
-    AMR_DISPATCH(c.q, c.storage, (interp_collide<Qc, Sc>(c, ilist, ni, clist, nblk, L, lp, bc)));
+bool launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int32_t *clist, int nblk, int L,
+                           const LevelParams &lp, const BCParams &bc, bool exchange) {
+    bool done = false;
+    AMR_DISPATCH(c.q, c.storage, (done = interp_collide<Qc, Sc>(c, ilist, ni, clist, nblk, L, lp, bc, exchange)));
+    return done;
 }
 
 void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {

@@ -165,17 +165,33 @@ void timed_launch(amr_handle *h, int kind, int blocks, int L, F &&fn) {
     if (a && b) h->timed.push_back({kind, a, b, (double)blocks, launch_bytes(h, kind, blocks, L)});
 }
 
-// fused: the ghost interpolation into level L+1 was launched together with
-// this sweep (launch_interp_collide)
-void collide_stream(amr_handle *h, int L, bool fused = false) {
+// Outside profiled runs (which time each kernel on its own) BGK sweeps save
+// launch gaps (~10 us each): a sweep with ordinary stores adds the momentum
+// exchange itself (the variant needs at most 3 more VGPRs, with no loss of
+// occupancy), and on small levels the ghost interpolation into level L+1 joins
+// the sweep.  Large levels keep the interpolation apart: the joined kernel
+// needs more registers (99 VGPRs for D3Q27 at 16-bit storage against 68) and
+// their launches are long.
+static bool join_launches(const amr_handle *h) { return h->c.coll == AMR_COLLIDE_BGK && !h->profiling; }
+
+static bool small_level(const amr_handle *h, int L) {
+    return h->nids[L] <= (h->c.dim == 3 ? 16384 : 65536);  // blocks of 64 / 16 cells
+}
+
+// fused: the sweep was launched together with the ghost interpolation into
+// level L+1 (launch_interp_collide); exchanged: that launch also added the
+// momentum exchange
+void collide_stream(amr_handle *h, int L, bool fused = false, bool exchanged = false) {
     const LevelParams lp = level_params(h);
+    const bool exchange = h->force_on && h->nsolid[L] > 0;
     if (!fused)
         timed_launch(h, 0, h->nids[L], L, [&] {
-            launch_collide_stream(h->c, h->c.order + (size_t)L * h->c.m.cap, h->nids[L], L, lp, h->bc);
+            exchanged = launch_collide_stream(h->c, h->c.order + (size_t)L * h->c.m.cap, h->nids[L], L, lp, h->bc,
+                                              exchange && join_launches(h));
         });
     h->par[L] ^= 1;
     // momentum exchange with solid blocks, from the buffer just written
-    if (h->force_on && h->nsolid[L] > 0)
+    if (exchange && !exchanged)
         launch_exchange(h->c, h->c.solidl + (size_t)L * h->c.m.cap, h->nsolid[L], L, level_params(h));
 }
 
@@ -186,20 +202,17 @@ void step_level(amr_handle *h, int L) {
         return;
     }
     const size_t cap = (size_t)h->c.m.cap;
-    // Small BGK levels outside profiled runs take the ghost interpolation into
-    // the same launch: one launch gap (~10 us) fewer per level visit.  Large
-    // levels keep two launches: the fused kernel needs more registers (99 VGPRs
-    // for D3Q27 at 16-bit storage against 68) and their launches are long.
-    const int fuse_max = h->c.dim == 3 ? 16384 : 65536;  // blocks of 64 / 16 cells
-    const bool fuse = h->niface[L] > 0 && h->nids[L] <= fuse_max && h->c.coll == AMR_COLLIDE_BGK && !h->profiling;
+    const bool fuse = h->niface[L] > 0 && join_launches(h) && small_level(h, L);
+    bool exchanged = false;
     if (fuse) {
         const LevelParams lp = level_params(h);
-        launch_interp_collide(h->c, h->c.iface + L * cap, h->niface[L], h->c.order + L * cap, h->nids[L], L, lp, h->bc);
+        exchanged = launch_interp_collide(h->c, h->c.iface + L * cap, h->niface[L], h->c.order + L * cap, h->nids[L],
+                                          L, lp, h->bc, h->force_on && h->nsolid[L] > 0);
     } else if (h->niface[L] > 0) {
         const LevelParams lp = level_params(h);
         timed_launch(h, 1, h->niface[L], L, [&] { launch_interp(h->c, h->c.iface + L * cap, h->niface[L], lp, 0); });
     }
-    collide_stream(h, L, fuse);
+    collide_stream(h, L, fuse, exchanged);
     step_level(h, L + 1);
     step_level(h, L + 1);
     if (h->niface[L] > 0) {
