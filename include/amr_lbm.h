@@ -246,6 +246,13 @@ amr_status lbm_step(amr_t *h, int32_t n_coarse_steps, uint32_t flags);
  *                          128 MiB (half the 256 MB Infinity Cache), 0 = every level, any
  *                          value >= 0 (else AMR_ERR_ARG).  Results do not depend on it; SET
  *                          re-captures the step graphs when the value changes
+ *   AMR_FIELD_SYNC_VELOCITY GET/SET int32[1]: 1 (the default) = with shifted storage, the
+ *                          averaging of the pre-adaptation synchronisation also computes the
+ *                          vorticity criterion's velocities of the children it reads (those
+ *                          without an N_SKIP link, whose cells the ghost interpolation that
+ *                          follows leaves alone), and the velocity pass covers only the rest;
+ *                          0 = the velocity pass computes every velocity.  Criterion values
+ *                          and tags do not depend on it; SET accepts 0 or 1 (else AMR_ERR_ARG)
  *   AMR_FIELD_KERNEL_STATS GET double[3][4]: for the collide-stream, interpolation and averaging
  *                          kernels: launches, summed event time (ms), blocks processed, and the
  *                          distribution bytes those blocks must move, accumulated over lbm_step
@@ -258,7 +265,7 @@ enum amr_field_kind {
     AMR_FIELD_LEVEL = 5, AMR_FIELD_STATUS = 6, AMR_FIELD_COORD = 7, AMR_FIELD_NBR = 8,
     AMR_FIELD_NBR_CHILD = 9, AMR_FIELD_IDSET = 10, AMR_FIELD_GAP = 11, AMR_FIELD_COUNTS = 12,
     AMR_FIELD_MASS_MOM = 13, AMR_FIELD_CRIT = 14, AMR_FIELD_PARITY = 15, AMR_FIELD_KERNEL_STATS = 16,
-    AMR_FIELD_FORCE = 17, AMR_FIELD_FORCE_ON = 18, AMR_FIELD_STREAM_BYTES = 19
+    AMR_FIELD_FORCE = 17, AMR_FIELD_FORCE_ON = 18, AMR_FIELD_STREAM_BYTES = 19, AMR_FIELD_SYNC_VELOCITY = 20
 };
 amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf, uint64_t bytes);
 

@@ -79,7 +79,10 @@ void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &
 // existing same-level neighbour cells that now stream from the new blocks
 void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const LevelParams &lp);
 // mode 0: interface parent cells; 1: every parent cell (non-refined entries are skipped)
-void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells);
+// U (shifted storage, all_cells = 1): the averaging also writes the criterion
+// velocities of the children it reads that have no N_SKIP link
+void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells,
+                    double *U = nullptr);
 // ghost interpolation into level L+1 (interface parents ilist) and the
 // collide-stream sweep of level L (launch order clist) in one launch; BGK;
 // exchange and the result as for launch_collide_stream
@@ -88,7 +91,8 @@ bool launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int
 void launch_fill_rest(const Ctx &c);
 // initial condition on root blocks [b0, b1) from rho_u_dev[((B - b0) Mb + l) 4]
 void launch_set_rho_u_root(const Ctx &c, const double *rho_u_dev, int b0, int b1);
-void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp);
+// averaged: skip the blocks whose velocities the averaging wrote (launch_average with U)
+void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, bool averaged = false);
 void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp);
 void launch_block_f(const Ctx &c, int set, int b0, int b1, double *stage, const LevelParams &lp);
 void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, void *stage, const LevelParams &lp);

@@ -991,6 +991,37 @@ __global__ void k_clear_fresh(const int32_t *__restrict__ list, int n, DevMesh m
 // the first one writes the parent cell.  Children without a targeted cell are
 // skipped whole.
 
+// The vorticity criterion reads velocities of leaf blocks and, across the six
+// faces of a leaf, of its same-level neighbours: a refined block none of whose
+// face neighbours is a leaf is never read.
+template <typename Lt>
+__device__ __forceinline__ bool velocity_read(const DevMesh &m, const int32_t *link, int B) {
+    if (!is_refined(m.status[B])) return true;
+    bool read = false;
+#pragma unroll
+    for (int a = 0; a < Lt::D; a++)
+        for (int sg = -1; sg <= 1; sg += 2) {
+            const int32_t code =
+                link[region_of<Lt>(a == 0 ? 1 + 3 * sg : 1, a == 1 ? 1 + 3 * sg : 1, a == 2 ? 1 + 3 * sg : 1)];
+            if (code >= 0 && code < m.cap && m.status[code] == ST_UNREF) read = true;
+        }
+    return read;
+}
+
+// FP64 velocity j / rho of cell `cell` from its populations fv, into U[3][capc]
+template <typename Lt>
+__device__ __forceinline__ void cell_velocity(const double *fv, double *U, int64_t capc, int64_t cell) {
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < Lt::Q; p++) {
+        rho += fv[p];
+        j[0] += fv[p] * Lt::cx(p);
+        j[1] += fv[p] * Lt::cy(p);
+        j[2] += fv[p] * Lt::cz(p);
+    }
+    for (int a = 0; a < 3; a++) U[a * capc + cell] = j[a] / rho;
+}
+
 // refined parents with children in the next level
 __device__ inline bool average_target(const DevMesh &m, int P, int nc) {
     const int c0 = m.nbrc[P];
@@ -1006,15 +1037,20 @@ __device__ __forceinline__ R xor_sum(R v, int mask) {
 template <int Q>
 constexpr int avg_children() { return Lat<Q>::D == 3 ? 4 : Lat<Q>::NC; }
 
-// children c0 .. c0 + NCW - 1 of parent P
-template <int Q, int S>
+// children c0 .. c0 + NCW - 1 of parent P.  VEL (shifted storage, every cell
+// averaged): also the criterion's FP64 velocity of each child cell that it
+// reads (velocity_read) and that the ghost interpolation after the averaging
+// does not rewrite (no N_SKIP link), from the values as stored, into U: the
+// same values and arithmetic as k_velocity, so that pass can skip those blocks.
+template <int Q, int S, bool VEL = false>
 __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, const typename Store<S>::T *src,
                                                typename Store<S>::T *dst, typename Store<S>::R r, int all_cells,
                                                BlockStage<Lat<Q>, avg_children<Q>() + 1> &st,
-                                               uint64_t (*tab)[27], int t) {
+                                               uint64_t (*tab)[27], int t, double *U = nullptr) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
+    static_assert(!VEL || ST::shift, "velocities from the averaging need the stored values (shifted storage)");
     constexpr int MB = Lt::MB, NCW = avg_children<Q>(), NC = Lt::NC;
     const int first = m.nbrc[P];
     if (t <= NCW) st.id[t] = t < NCW ? first + c0 + t : P;
@@ -1048,6 +1084,14 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, 
 #pragma unroll
         for (int p = 0; p < Q; p++) g[p] = R(0);
     }
+    if constexpr (VEL) {
+        if (!(st.flag[cw] & BF_NSKIP) && velocity_read<Lt>(m, st.link[cw], child)) {
+            double fv[Q];
+#pragma unroll
+            for (int p = 0; p < Q; p++) fv[p] = double(g[p]) + Lt::w(p);
+            cell_velocity<Lt>(fv, U, m.capc, (int64_t)child * MB + lf);
+        }
+    }
     R drho, ux, uy, uz;
     moments_g<Lt, R>(g, drho, ux, uy, uz);
     const R uu = ux * ux + uy * uy + uz * uz;
@@ -1072,10 +1116,10 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, 
 // SIMD: left alone the compiler takes 88 VGPRs (5 waves) for D3Q27 FP32; at 80
 // the launch is 9 % shorter on the cylinder set-up (no spills; at 64 it spills
 // and is slower).
-template <int Q, int S>
+template <int Q, int S, bool VEL = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_average(const int32_t *__restrict__ list, int n, DevMesh m,
                                                  typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
-                                                 int all_cells) {
+                                                 int all_cells, double *U) {
     using Lt = Lat<Q>;
     using R = typename Store<S>::R;
     constexpr int SPLIT = Lt::NC / avg_children<Q>();
@@ -1086,8 +1130,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     const int P = list[item];
     if (!average_target(m, P, Lt::NC)) return;
     const int L = m.level[P];
-    average_parent<Q, S>(m, P, part * avg_children<Q>(), lp.par[L + 1] ? f1 : f0, lp.par[L] ? f1 : f0,
-                         R(lp.r_fc[L]), all_cells, st, tab, threadIdx.x);
+    average_parent<Q, S, VEL>(m, P, part * avg_children<Q>(), lp.par[L + 1] ? f1 : f0, lp.par[L] ? f1 : f0,
+                              R(lp.r_fc[L]), all_cells, st, tab, threadIdx.x, U);
 }
 
 // Batched interface averaging of level L+1 into level L, persistent
@@ -1331,9 +1375,12 @@ __device__ inline void cell_f64(const DevMesh &m, const int32_t *link, int B, in
         fv[p] = double(ST::ld(f + entry_slot<Lt>(m, link, B, h, p, l))) + (ST::shift ? Lt::w(p) : 0.0);
 }
 
+// averaged: blocks below level 0 without an N_SKIP link already have their
+// velocities (k_average with VEL) and are skipped
 template <int Q, int S>
 __global__ __launch_bounds__(256) void k_velocity(const int32_t *__restrict__ list, int n, DevMesh m,
-                                                  const typename Store<S>::T *__restrict__ f, double *U) {
+                                                  const typename Store<S>::T *__restrict__ f, double *U,
+                                                  int averaged) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     constexpr int MB = Lt::MB, BPW = 256 / MB;
@@ -1350,20 +1397,8 @@ __global__ __launch_bounds__(256) void k_velocity(const int32_t *__restrict__ li
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
     const int B = st.id[s];
     if (B < 0) return;
-    // The criterion reads velocities of leaf blocks and, across the six faces
-    // of a leaf, of its same-level neighbours: a refined block none of whose
-    // face neighbours is a leaf is never read.
-    if (is_refined(m.status[B])) {
-        bool read = false;
-#pragma unroll
-        for (int a = 0; a < Lt::D; a++)
-            for (int sg = -1; sg <= 1; sg += 2) {
-                const int32_t code = st.link[s][region_of<Lt>(a == 0 ? 1 + 3 * sg : 1, a == 1 ? 1 + 3 * sg : 1,
-                                                              a == 2 ? 1 + 3 * sg : 1)];
-                if (code >= 0 && code < m.cap && m.status[code] == ST_UNREF) read = true;
-            }
-        if (!read) return;
-    }
+    if (averaged && m.level[B] > 0 && !(st.flag[s] & BF_NSKIP)) return;
+    if (!velocity_read<Lt>(m, st.link[s], B)) return;
     double fv[Q];
     bool done = false;
     if constexpr (Lt::D == 3) {
@@ -1377,16 +1412,7 @@ __global__ __launch_bounds__(256) void k_velocity(const int32_t *__restrict__ li
         }
     }
     if (!done) cell_f64<Lt, ST>(m, st.link[s], B, st.hid[s], l, f, fv);
-    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int p = 0; p < Q; p++) {
-        rho += fv[p];
-        j[0] += fv[p] * Lt::cx(p);
-        j[1] += fv[p] * Lt::cy(p);
-        j[2] += fv[p] * Lt::cz(p);
-    }
-    const int64_t cell = (int64_t)B * MB + l;
-    for (int a = 0; a < 3; a++) U[a * m.capc + cell] = j[a] / rho;
+    cell_velocity<Lt>(fv, U, m.capc, (int64_t)B * MB + l);
 }
 
 template <int Q>
@@ -1873,14 +1899,25 @@ void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const L
     k_clear_fresh<<<(n * c.nc + 255) / 256, 256, 0, c.stream>>>(list, n, c.m, c.nc);
 }
 
-void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells) {
-    if (n <= 0) return;
+template <int Q, int S>
+static void average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells, double *U) {
+    using T = typename Store<S>::T;
     // one lane per fine cell of the workgroup's children; 3-D: two workgroups per parent
     const int split = c.dim == 3 ? 2 : 1;
     const int threads = c.nc / split * c.mb;
-    AMR_DISPATCH(c.q, c.storage,
-                 (k_average<Qc, Sc><<<n * split, threads, 0, c.stream>>>(list, n, c.m, TPTR(Sc, c.f[0]),
-                                                                         TPTR(Sc, c.f[1]), lp, all_cells)));
+    T *f0 = (T *)c.f[0], *f1 = (T *)c.f[1];
+    if constexpr (Store<S>::shift) {
+        if (U) {
+            k_average<Q, S, true><<<n * split, threads, 0, c.stream>>>(list, n, c.m, f0, f1, lp, 1, U);
+            return;
+        }
+    }
+    k_average<Q, S><<<n * split, threads, 0, c.stream>>>(list, n, c.m, f0, f1, lp, all_cells, nullptr);
+}
+
+void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells, double *U) {
+    if (n <= 0) return;
+    AMR_DISPATCH(c.q, c.storage, (average<Qc, Sc>(c, list, n, lp, all_cells, U)));
 }
 
 void launch_fill_rest(const Ctx &c) {
@@ -1897,11 +1934,11 @@ void launch_set_rho_u_root(const Ctx &c, const double *ru, int b0, int b1) {
                                                                                          b0, b1)));
 }
 
-void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp) {
+void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, bool averaged) {
     if (n <= 0) return;
     AMR_DISPATCH(c.q, c.storage,
-                 (k_velocity<Qc, Sc><<<grid_blocks(n, c.mb), 256, 0, c.stream>>>(list, n, c.m,
-                                                                                  TPTR(Sc, c.f[lp.par[L]]), c.U)));
+                 (k_velocity<Qc, Sc><<<grid_blocks(n, c.mb), 256, 0, c.stream>>>(
+                     list, n, c.m, TPTR(Sc, c.f[lp.par[L]]), c.U, averaged ? 1 : 0)));
 }
 
 void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &) {

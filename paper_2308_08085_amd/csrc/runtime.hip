@@ -526,8 +526,15 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
     const size_t cap = (size_t)c.m.cap;
     amr_status ms;
     if ((ms = mark(h, 0)) != AMR_OK) return ms;
-    // pre-adaptation synchronisation
-    for (int L = h->lmax - 2; L >= 0; L--) launch_average(c, c.ids + L * cap, h->nids[L], level_params(h), 1);
+    // pre-adaptation synchronisation.  With the vorticity criterion and shifted
+    // storage the averaging, which reads every child, also writes the
+    // velocities of the children whose cells the ghost interpolation below
+    // leaves alone; the velocity pass then covers level 0 and the rest.
+    const bool vort = !tags_in && (p->kind == AMR_TAG_VORTICITY_REL || p->kind == AMR_TAG_LADDER);
+    const bool shifted = c.storage == AMR_F32S || c.storage == AMR_F16S || c.storage == AMR_BF16S;
+    const bool averaged = vort && shifted && h->sync_velocity;
+    for (int L = h->lmax - 2; L >= 0; L--)
+        launch_average(c, c.ids + L * cap, h->nids[L], level_params(h), 1, averaged ? c.U : nullptr);
     if ((ms = mark(h, 1)) != AMR_OK) return ms;
     for (int L = 0; L <= h->lmax - 2; L++)
         if (h->niface[L] > 0) launch_interp(c, c.iface + L * cap, h->niface[L], level_params(h), 0);
@@ -537,7 +544,7 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
         HIP_TRY(hipMemcpyAsync(c.m.tag, tags_in, cap, hipMemcpyHostToDevice, c.stream));
     } else if (p->kind == AMR_TAG_VORTICITY_REL || p->kind == AMR_TAG_LADDER) {
         const LevelParams lp = level_params(h);
-        for (int L = 0; L < h->lmax; L++) launch_velocity(c, c.ids + L * cap, h->nids[L], L, lp);
+        for (int L = 0; L < h->lmax; L++) launch_velocity(c, c.ids + L * cap, h->nids[L], L, lp, averaged);
         for (int L = 0; L < h->lmax; L++) launch_vorticity(c, c.ids + L * cap, h->nids[L], L, lp);
         if (p->kind == AMR_TAG_LADDER) {
             LadderParams lad;
@@ -678,6 +685,17 @@ amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf
             h->force_on = *v == 1;
             drop_graphs(h);  // captured steps hold the exchange launches, or not
         }
+        return AMR_OK;
+    }
+    if (kind == AMR_FIELD_SYNC_VELOCITY) {
+        if (!buf || bytes < 4) return fail(AMR_ERR_ARG, "AMR_FIELD_SYNC_VELOCITY needs an int32 buffer");
+        int32_t *v = (int32_t *)buf;
+        if (op == AMR_GET) {
+            *v = h->sync_velocity ? 1 : 0;
+            return AMR_OK;
+        }
+        if (*v != 0 && *v != 1) return fail(AMR_ERR_ARG, "AMR_FIELD_SYNC_VELOCITY takes 0 or 1, not %d", *v);
+        h->sync_velocity = *v == 1;
         return AMR_OK;
     }
     if (kind == AMR_FIELD_STREAM_BYTES) {

@@ -44,6 +44,7 @@ struct amr_handle {
     int par[kMaxLevels];
     double force_sweeps[kMaxLevels] = {0};  // collide-stream sweeps per level since the force reset
     bool force_on = true;                   // accumulate the momentum exchange every sweep
+    bool sync_velocity = true;              // criterion velocities from the synchronisation's averaging
     int batches = 0;                        // batches this handle is a member of
     double tau[kMaxLevels];
     BCParams bc;

@@ -445,3 +445,46 @@ def test_exchange_in_sweep_equals_separate_pass(dim, q, storage):
         g.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dim,q,storage,kind", [(2, 9, "f32s", abi.TAG_VORTICITY_REL),
+                                                (3, 27, "f32s", abi.TAG_VORTICITY_REL),
+                                                (3, 19, "f16s", abi.TAG_LADDER),
+                                                (3, 27, "bf16s", abi.TAG_VORTICITY_REL)])
+def test_criterion_velocities_from_the_averaging(dim, q, storage, kind):
+    """with shifted storage the synchronisation's averaging computes the
+    criterion velocities of the children it reads, and the velocity pass only
+    the rest (AMR_FIELD_SYNC_VELOCITY); criterion values, tags and fields equal
+    those of the velocity pass alone bit for bit, over several adaptations"""
+    if dim == 2:
+        case = W.cylinder(2, 9, (64, 32), 8, 16, 3, 100.0, storage=storage, cap=3000, seed=9)
+    else:
+        case = W.cylinder(3, q, (32, 16, 16), 4, 8, 3, 100.0, storage=storage, cap=12000, seed=10)
+    runs = []
+    for fused in (False, True):
+        g = abi.AmrLbm(case)
+        g.set_root_rho_u(case.initial_rho_u())
+        assert g.sync_velocity()
+        if not fused:
+            assert not g.sync_velocity(False)
+        for _ in range(case.lmax - 1):
+            g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=0)
+            g.adapt()
+        out = []
+        for _ in range(3):
+            g.step(8, graph=True)
+            tags = g.tag(kind, theta=0.1, n_start=-3.0, n_inc=1.0)
+            out += [g.crit(), tags]
+            g.adapt()
+        assert len(g.mesh()["ids"][2]) > 0
+        out.append(g.get_block_f_all())
+        runs.append(out)
+        g.close()
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+    with pytest.raises(abi.AmrError):
+        g = abi.AmrLbm(case)
+        try:
+            g._fields(abi.AMR_SET, abi.F_SYNC_VELOCITY, np.array([2], np.int32))
+        finally:
+            g.close()
