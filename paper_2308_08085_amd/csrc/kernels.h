@@ -91,8 +91,10 @@ bool launch_interp_collide(const Ctx &c, const int32_t *ilist, int ni, const int
 void launch_fill_rest(const Ctx &c);
 // initial condition on root blocks [b0, b1) from rho_u_dev[((B - b0) Mb + l) 4]
 void launch_set_rho_u_root(const Ctx &c, const double *rho_u_dev, int b0, int b1);
-// averaged: skip the blocks whose velocities the averaging wrote (launch_average with U)
-void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, bool averaged = false);
+// criterion velocities of level L's blocks in `list`; children: `list` holds
+// the interface parents of level L-1 and only their children with an N_SKIP
+// link are done (the rest came from launch_average with U)
+void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, bool children = false);
 void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp);
 void launch_block_f(const Ctx &c, int set, int b0, int b1, double *stage, const LevelParams &lp);
 void launch_out_gather(const Ctx &c, int kind, int b0, int b1, int32_t off0, void *stage, const LevelParams &lp);

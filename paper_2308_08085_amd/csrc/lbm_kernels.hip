@@ -1375,19 +1375,37 @@ __device__ inline void cell_f64(const DevMesh &m, const int32_t *link, int B, in
         fv[p] = double(ST::ld(f + entry_slot<Lt>(m, link, B, h, p, l))) + (ST::shift ? Lt::w(p) : 0.0);
 }
 
-// averaged: blocks below level 0 without an N_SKIP link already have their
-// velocities (k_average with VEL) and are skipped
+// children = 0: `list` holds the blocks.  children = 1: `list` holds parents
+// (the interface parents of the level above) and the kernel takes those of
+// their children that have an N_SKIP link: after k_average with VEL, the only
+// blocks below level 0 whose velocities are still missing.
 template <int Q, int S>
 __global__ __launch_bounds__(256) void k_velocity(const int32_t *__restrict__ list, int n, DevMesh m,
                                                   const typename Store<S>::T *__restrict__ f, double *U,
-                                                  int averaged) {
+                                                  int children) {
     using Lt = Lat<Q>;
     using ST = Store<S>;
     constexpr int MB = Lt::MB, BPW = 256 / MB;
     __shared__ BlockStage<Lt, BPW> st;
+    __shared__ int any;
     const int base = blockIdx.x * BPW;
-    if ((int)threadIdx.x < BPW) st.id[threadIdx.x] = base + (int)threadIdx.x < n ? list[base + threadIdx.x] : -1;
+    if (threadIdx.x == 0) any = 0;
     __syncthreads();
+    if ((int)threadIdx.x < BPW) {
+        const int64_t i = (int64_t)base + threadIdx.x;
+        int B = -1;
+        if (!children) {
+            if (i < n) B = list[i];
+        } else if (i < (int64_t)n * Lt::NC) {
+            const int c0 = m.nbrc[list[i / Lt::NC]];
+            const int C = c0 + (int)(i % Lt::NC);
+            if (c0 >= 0 && (m.bflag[C] & BF_NSKIP)) B = C;
+        }
+        st.id[threadIdx.x] = B;
+        if (B >= 0) any = 1;
+    }
+    __syncthreads();
+    if (!any) return;  // the whole workgroup: nothing to stage
     stage_blocks<Lt, BPW>(m, st);
     __shared__ uint64_t tab[Lt::D == 3 ? BPW : 1][27];
     if constexpr (Lt::D == 3) {
@@ -1397,7 +1415,6 @@ __global__ __launch_bounds__(256) void k_velocity(const int32_t *__restrict__ li
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
     const int B = st.id[s];
     if (B < 0) return;
-    if (averaged && m.level[B] > 0 && !(st.flag[s] & BF_NSKIP)) return;
     if (!velocity_read<Lt>(m, st.link[s], B)) return;
     double fv[Q];
     bool done = false;
@@ -1429,6 +1446,30 @@ __global__ __launch_bounds__(256) void k_vorticity(const int32_t *__restrict__ l
     const int s = threadIdx.x / MB, l = threadIdx.x % MB;
     const int B = st.id[s];
     const bool leaf = B >= 0 && m.status[B] == ST_UNREF;
+    const int ci[3] = {l & 3, (l >> 2) & 3, l >> 4};
+    // the neighbour cells along +-x, +-y (+-z): those in other blocks are read
+    // here, all loads at once and before the barrier; those inside the block
+    // come from the block's own velocities in LDS below
+    double nv[3][2][3] = {};
+    int nlc[3][2];
+    bool nhas[3][2], nin[3][2];
+#pragma unroll
+    for (int a = 0; a < Lt::D; a++)
+#pragma unroll
+        for (int sg = 0; sg < 2; sg++) {
+            int t[3] = {ci[0], ci[1], ci[2]};
+            t[a] += sg == 0 ? 1 : -1;
+            const int rg = region_of<Lt>(t[0], t[1], t[2]);
+            const int32_t code = leaf ? st.link[s][rg] : -1;
+            nhas[a][sg] = code >= 0 && code < m.cap;
+            nin[a][sg] = rg == kCenterSlot<Lt>;
+            nlc[a][sg] = (t[0] & 3) + 4 * (t[1] & 3) + 16 * (t[2] & 3);
+            if (nhas[a][sg] && !nin[a][sg]) {
+                const int64_t nc = (int64_t)code * MB + nlc[a][sg];
+#pragma unroll
+                for (int b = 0; b < 3; b++) nv[a][sg][b] = U[b * m.capc + nc];
+            }
+        }
     // the velocities of the block's own cells, for the neighbours inside it
     __shared__ double us[BPW][3][MB];
     if (leaf)
@@ -1436,31 +1477,24 @@ __global__ __launch_bounds__(256) void k_vorticity(const int32_t *__restrict__ l
     __syncthreads();
     double w = 0.0;
     if (leaf) {
-        const int ci[3] = {l & 3, (l >> 2) & 3, l >> 4};
         double u0[3];
         for (int b = 0; b < 3; b++) u0[b] = us[s][b][l];
         double gr[3][3];
         for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) gr[a][b] = 0.0;
+#pragma unroll
         for (int a = 0; a < Lt::D; a++) {
             double up[3], um[3];
             bool hp = false, hm = false;
+#pragma unroll
             for (int sg = 0; sg < 2; sg++) {
-                int t[3] = {ci[0], ci[1], ci[2]};
-                t[a] += sg == 0 ? 1 : -1;
-                const int rg = region_of<Lt>(t[0], t[1], t[2]);
-                const int32_t code = st.link[s][rg];
-                if (code < 0 || code >= m.cap) continue;
-                const int lc = (t[0] & 3) + 4 * (t[1] & 3) + 16 * (t[2] & 3);
+                if (!nhas[a][sg]) continue;
                 double *dstv = sg == 0 ? up : um;
-                if (rg == kCenterSlot<Lt>) {
-                    for (int b = 0; b < 3; b++) dstv[b] = us[s][b][lc];
-                } else {
-                    const int64_t nc = (int64_t)code * MB + lc;
-                    for (int b = 0; b < 3; b++) dstv[b] = U[b * m.capc + nc];
-                }
+#pragma unroll
+                for (int b = 0; b < 3; b++) dstv[b] = nin[a][sg] ? us[s][b][nlc[a][sg]] : nv[a][sg][b];
                 if (sg == 0) hp = true; else hm = true;
             }
+#pragma unroll
             for (int b = 0; b < 3; b++) {
                 if (hp && hm) gr[a][b] = (up[b] - um[b]) / 2.0;
                 else if (hp) gr[a][b] = up[b] - u0[b];
@@ -1934,11 +1968,12 @@ void launch_set_rho_u_root(const Ctx &c, const double *ru, int b0, int b1) {
                                                                                          b0, b1)));
 }
 
-void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, bool averaged) {
+void launch_velocity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &lp, bool children) {
     if (n <= 0) return;
+    const int64_t items = children ? (int64_t)n * c.nc : n;
     AMR_DISPATCH(c.q, c.storage,
-                 (k_velocity<Qc, Sc><<<grid_blocks(n, c.mb), 256, 0, c.stream>>>(
-                     list, n, c.m, TPTR(Sc, c.f[lp.par[L]]), c.U, averaged ? 1 : 0)));
+                 (k_velocity<Qc, Sc><<<grid_blocks(items, c.mb), 256, 0, c.stream>>>(
+                     list, n, c.m, TPTR(Sc, c.f[lp.par[L]]), c.U, children ? 1 : 0)));
 }
 
 void launch_vorticity(const Ctx &c, const int32_t *list, int n, int L, const LevelParams &) {

@@ -544,7 +544,12 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
         HIP_TRY(hipMemcpyAsync(c.m.tag, tags_in, cap, hipMemcpyHostToDevice, c.stream));
     } else if (p->kind == AMR_TAG_VORTICITY_REL || p->kind == AMR_TAG_LADDER) {
         const LevelParams lp = level_params(h);
-        for (int L = 0; L < h->lmax; L++) launch_velocity(c, c.ids + L * cap, h->nids[L], L, lp, averaged);
+        for (int L = 0; L < h->lmax; L++) {
+            if (averaged && L > 0)
+                launch_velocity(c, c.iface + (L - 1) * cap, h->niface[L - 1], L, lp, true);
+            else
+                launch_velocity(c, c.ids + L * cap, h->nids[L], L, lp);
+        }
         for (int L = 0; L < h->lmax; L++) launch_vorticity(c, c.ids + L * cap, h->nids[L], L, lp);
         if (p->kind == AMR_TAG_LADDER) {
             LadderParams lad;
