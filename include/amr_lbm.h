@@ -246,8 +246,8 @@ amr_status lbm_step(amr_t *h, int32_t n_coarse_steps, uint32_t flags);
  *                          128 MiB (half the 256 MB Infinity Cache), 0 = every level, any
  *                          value >= 0 (else AMR_ERR_ARG).  Results do not depend on it; SET
  *                          re-captures the step graphs when the value changes
- *   AMR_FIELD_SYNC_VELOCITY GET/SET int32[1]: 1 (the default) = with shifted storage, the
- *                          averaging of the pre-adaptation synchronisation also computes the
+ *   AMR_FIELD_SYNC_VELOCITY GET/SET int32[1]: 1 (the default) = the averaging of the
+ *                          pre-adaptation synchronisation also computes the
  *                          vorticity criterion's velocities of the children it reads (those
  *                          without an N_SKIP link, whose cells the ghost interpolation that
  *                          follows leaves alone), and the velocity pass covers only the rest;

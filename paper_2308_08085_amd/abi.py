@@ -256,7 +256,7 @@ class AmrLbm:
 
     def sync_velocity(self, on=None):
         """whether the synchronisation's averaging also computes the criterion
-        velocities (shifted storage); with `on`, switch it first"""
+        velocities; with `on`, switch it first"""
         if on is not None:
             self._fields(AMR_SET, F_SYNC_VELOCITY, np.array([1 if on else 0], np.int32))
         return bool(self._fields(AMR_GET, F_SYNC_VELOCITY, np.zeros(1, np.int32))[0])

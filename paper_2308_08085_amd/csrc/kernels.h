@@ -79,8 +79,8 @@ void launch_interp(const Ctx &c, const int32_t *list, int n, const LevelParams &
 // existing same-level neighbour cells that now stream from the new blocks
 void launch_refresh_neighbours(const Ctx &c, const int32_t *list, int n, const LevelParams &lp);
 // mode 0: interface parent cells; 1: every parent cell (non-refined entries are skipped)
-// U (shifted storage, all_cells = 1): the averaging also writes the criterion
-// velocities of the children it reads that have no N_SKIP link
+// U (all_cells = 1): the averaging also writes the criterion velocities of
+// the children it reads that have no N_SKIP link
 void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells,
                     double *U = nullptr);
 // ghost interpolation into level L+1 (interface parents ilist) and the

@@ -72,11 +72,12 @@ __device__ __forceinline__ R rescale_neq(int p, R g, R r, R drho, R ux, R uy, R 
     return fmadd(w, y, r * fmadd(-w, y, g));
 }
 
-template <typename Lt, typename ST>
+// RAW: the stored value itself, also for unshifted storage
+template <typename Lt, typename ST, bool RAW = false>
 __device__ __forceinline__ typename ST::R load_g(const typename ST::T *f, int64_t slot, int p) {
     using R = typename ST::R;
     const R v = ST::ld(f + slot);
-    return ST::shift ? v : v - R(Lt::w(p));
+    return (ST::shift || RAW) ? v : v - R(Lt::w(p));
 }
 
 template <typename Lt, typename ST, bool NT = false>
@@ -89,18 +90,18 @@ __device__ __forceinline__ void store_g(typename ST::T *f, int64_t slot, int p, 
 }
 
 // gather / scatter all populations of one cell
-template <typename Lt, typename ST>
+template <typename Lt, typename ST, bool RAW = false>
 __device__ __forceinline__ void gather_cell(const DevMesh &m, const int32_t *link, int B, int h, int l,
                                             const typename ST::T *f, typename ST::R *g) {
 #pragma unroll
-    for (int p = 0; p < Lt::Q; p++) g[p] = load_g<Lt, ST>(f, entry_slot<Lt>(m, link, B, h, p, l), p);
+    for (int p = 0; p < Lt::Q; p++) g[p] = load_g<Lt, ST, RAW>(f, entry_slot<Lt>(m, link, B, h, p, l), p);
 }
 
 // The same for a block whose only links outside the fluid are domain faces or
 // solid blocks (no coarser neighbour): each population comes from a same-level
 // block or from the cell's own opposite slot, a select between two addresses
 // rather than a branch per population.
-template <typename Lt, typename ST>
+template <typename Lt, typename ST, bool RAW = false>
 __device__ __forceinline__ void gather_cell_nohalo(const DevMesh &m, const int32_t *link, int B, int l,
                                                    const typename ST::T *f, typename ST::R *g) {
 #pragma unroll
@@ -111,19 +112,19 @@ __device__ __forceinline__ void gather_cell_nohalo(const DevMesh &m, const int32
         const int blk = in ? code : B;
         const int q = in ? p : Lt::opp(p);
         const int cell = in ? (sx & 3) + 4 * (sy & 3) + 16 * (sz & 3) : l;
-        g[p] = load_g<Lt, ST>(f, mslot<Lt>(blk, q, cell), p);
+        g[p] = load_g<Lt, ST, RAW>(f, mslot<Lt>(blk, q, cell), p);
     }
 }
 
 // gather of a cell of a block with flags `flag`: the select form unless the
 // block has a coarser neighbour
-template <typename Lt, typename ST>
+template <typename Lt, typename ST, bool RAW = false>
 __device__ __forceinline__ void gather_cell_flag(const DevMesh &m, const int32_t *link, int B, int h, uint8_t flag,
                                                  int l, const typename ST::T *f, typename ST::R *g) {
     if (flag & BF_NSKIP)
-        gather_cell<Lt, ST>(m, link, B, h, l, f, g);
+        gather_cell<Lt, ST, RAW>(m, link, B, h, l, f, g);
     else
-        gather_cell_nohalo<Lt, ST>(m, link, B, l, f, g);
+        gather_cell_nohalo<Lt, ST, RAW>(m, link, B, l, f, g);
 }
 
 template <typename Lt, typename ST>
@@ -188,11 +189,11 @@ __device__ __forceinline__ void gather_interior_by(const InteriorLane &u, Out *o
     }
 }
 
-// the shifted populations g (as load_g)
-template <typename Lt, typename ST>
+// the shifted populations g (as load_g; RAW: the stored values)
+template <typename Lt, typename ST, bool RAW = false>
 __device__ __forceinline__ void gather_interior(const InteriorLane &u, typename ST::R *g) {
     using R = typename ST::R;
-    gather_interior_by<Lt, ST, 0>(u, g, [](R v, int p) { return ST::shift ? v : v - R(Lt::w(p)); });
+    gather_interior_by<Lt, ST, 0>(u, g, [](R v, int p) { return (ST::shift || RAW) ? v : v - R(Lt::w(p)); });
 }
 
 // BGK relaxation of one cell in the shifted variables: moments, then
@@ -1037,11 +1038,11 @@ __device__ __forceinline__ R xor_sum(R v, int mask) {
 template <int Q>
 constexpr int avg_children() { return Lat<Q>::D == 3 ? 4 : Lat<Q>::NC; }
 
-// children c0 .. c0 + NCW - 1 of parent P.  VEL (shifted storage, every cell
-// averaged): also the criterion's FP64 velocity of each child cell that it
-// reads (velocity_read) and that the ghost interpolation after the averaging
-// does not rewrite (no N_SKIP link), from the values as stored, into U: the
-// same values and arithmetic as k_velocity, so that pass can skip those blocks.
+// children c0 .. c0 + NCW - 1 of parent P.  VEL (every cell averaged): also
+// the criterion's FP64 velocity of each child cell that it reads
+// (velocity_read) and that the ghost interpolation after the averaging does
+// not rewrite (no N_SKIP link), from the values as stored, into U: the same
+// values and arithmetic as k_velocity, so that pass can skip those blocks.
 template <int Q, int S, bool VEL = false>
 __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, const typename Store<S>::T *src,
                                                typename Store<S>::T *dst, typename Store<S>::R r, int all_cells,
@@ -1050,7 +1051,9 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, 
     using Lt = Lat<Q>;
     using ST = Store<S>;
     using R = typename ST::R;
-    static_assert(!VEL || ST::shift, "velocities from the averaging need the stored values (shifted storage)");
+    // with unshifted storage the velocities need the stored values: gather
+    // those, then form g exactly as load_g does
+    constexpr bool RAW = VEL && !ST::shift;
     constexpr int MB = Lt::MB, NCW = avg_children<Q>(), NC = Lt::NC;
     const int first = m.nbrc[P];
     if (t <= NCW) st.id[t] = t < NCW ? first + c0 + t : P;
@@ -1075,11 +1078,11 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, 
         bool done = false;
         if constexpr (Lt::D == 3) {
             if (!(st.flag[cw] & (BF_BOUNDARY | BF_NSKIP))) {
-                gather_interior<Lt, ST>(interior_lane<typename ST::T>(tab[cw], lf & 3, (lf >> 2) & 3, lf >> 4), g);
+                gather_interior<Lt, ST, RAW>(interior_lane<typename ST::T>(tab[cw], lf & 3, (lf >> 2) & 3, lf >> 4), g);
                 done = true;
             }
         }
-        if (!done) gather_cell_flag<Lt, ST>(m, st.link[cw], child, st.hid[cw], st.flag[cw], lf, src, g);
+        if (!done) gather_cell_flag<Lt, ST, RAW>(m, st.link[cw], child, st.hid[cw], st.flag[cw], lf, src, g);
     } else {
 #pragma unroll
         for (int p = 0; p < Q; p++) g[p] = R(0);
@@ -1088,8 +1091,14 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, 
         if (!(st.flag[cw] & BF_NSKIP) && velocity_read<Lt>(m, st.link[cw], child)) {
             double fv[Q];
 #pragma unroll
-            for (int p = 0; p < Q; p++) fv[p] = double(g[p]) + Lt::w(p);
+            for (int p = 0; p < Q; p++) fv[p] = double(g[p]) + (ST::shift ? Lt::w(p) : 0.0);
             cell_velocity<Lt>(fv, U, m.capc, (int64_t)child * MB + lf);
+        }
+        if constexpr (RAW) {
+            if ((im >> lead) & 1ull) {
+#pragma unroll
+                for (int p = 0; p < Q; p++) g[p] = g[p] - R(Lt::w(p));
+            }
         }
     }
     R drho, ux, uy, uz;
@@ -1117,7 +1126,7 @@ __device__ __forceinline__ void average_parent(const DevMesh &m, int P, int c0, 
 // the launch is 9 % shorter on the cylinder set-up (no spills; at 64 it spills
 // and is slower).
 template <int Q, int S, bool VEL = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_average(const int32_t *__restrict__ list, int n, DevMesh m,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == AMR_F64 ? 1 : 6))) void k_average(const int32_t *__restrict__ list, int n, DevMesh m,
                                                  typename Store<S>::T *f0, typename Store<S>::T *f1, LevelParams lp,
                                                  int all_cells, double *U) {
     using Lt = Lat<Q>;
@@ -1940,13 +1949,8 @@ static void average(const Ctx &c, const int32_t *list, int n, const LevelParams 
     const int split = c.dim == 3 ? 2 : 1;
     const int threads = c.nc / split * c.mb;
     T *f0 = (T *)c.f[0], *f1 = (T *)c.f[1];
-    if constexpr (Store<S>::shift) {
-        if (U) {
-            k_average<Q, S, true><<<n * split, threads, 0, c.stream>>>(list, n, c.m, f0, f1, lp, 1, U);
-            return;
-        }
-    }
-    k_average<Q, S><<<n * split, threads, 0, c.stream>>>(list, n, c.m, f0, f1, lp, all_cells, nullptr);
+    if (U) k_average<Q, S, true><<<n * split, threads, 0, c.stream>>>(list, n, c.m, f0, f1, lp, 1, U);
+    else k_average<Q, S><<<n * split, threads, 0, c.stream>>>(list, n, c.m, f0, f1, lp, all_cells, nullptr);
 }
 
 void launch_average(const Ctx &c, const int32_t *list, int n, const LevelParams &lp, int all_cells, double *U) {

@@ -526,13 +526,12 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
     const size_t cap = (size_t)c.m.cap;
     amr_status ms;
     if ((ms = mark(h, 0)) != AMR_OK) return ms;
-    // pre-adaptation synchronisation.  With the vorticity criterion and shifted
-    // storage the averaging, which reads every child, also writes the
-    // velocities of the children whose cells the ghost interpolation below
-    // leaves alone; the velocity pass then covers level 0 and the rest.
+    // pre-adaptation synchronisation.  With the vorticity criterion the
+    // averaging, which reads every child, also writes the velocities of the
+    // children whose cells the ghost interpolation below leaves alone; the
+    // velocity pass then covers level 0 and the rest.
     const bool vort = !tags_in && (p->kind == AMR_TAG_VORTICITY_REL || p->kind == AMR_TAG_LADDER);
-    const bool shifted = c.storage == AMR_F32S || c.storage == AMR_F16S || c.storage == AMR_BF16S;
-    const bool averaged = vort && shifted && h->sync_velocity;
+    const bool averaged = vort && h->sync_velocity;
     for (int L = h->lmax - 2; L >= 0; L--)
         launch_average(c, c.ids + L * cap, h->nids[L], level_params(h), 1, averaged ? c.U : nullptr);
     if ((ms = mark(h, 1)) != AMR_OK) return ms;

@@ -450,10 +450,13 @@ def test_exchange_in_sweep_equals_separate_pass(dim, q, storage):
 @pytest.mark.parametrize("dim,q,storage,kind", [(2, 9, "f32s", abi.TAG_VORTICITY_REL),
                                                 (3, 27, "f32s", abi.TAG_VORTICITY_REL),
                                                 (3, 19, "f16s", abi.TAG_LADDER),
-                                                (3, 27, "bf16s", abi.TAG_VORTICITY_REL)])
+                                                (3, 27, "bf16s", abi.TAG_VORTICITY_REL),
+                                                (3, 19, "f64", abi.TAG_VORTICITY_REL),
+                                                (2, 9, "f32", abi.TAG_LADDER)])
 def test_criterion_velocities_from_the_averaging(dim, q, storage, kind):
-    """with shifted storage the synchronisation's averaging computes the
-    criterion velocities of the children it reads, and the velocity pass only
+    """the synchronisation's averaging computes the criterion velocities of
+    the children it reads (from the stored values, also for unshifted
+    storage), and the velocity pass only
     the rest (AMR_FIELD_SYNC_VELOCITY); criterion values, tags and fields equal
     those of the velocity pass alone bit for bit, over several adaptations"""
     if dim == 2:
