@@ -10,6 +10,7 @@ struct DevCounters {
     int32_t nids[kMaxLevels];
     int32_t niface[kMaxLevels];
     int32_t nsolid[kMaxLevels];
+    int32_t nref[kMaxLevels];  // refined blocks per level (list refl)
     int32_t gtop;
     int32_t n_ref, n_coa, n_rev;
     int32_t nfreed;
@@ -39,6 +40,7 @@ struct Ctx {
     int32_t *ids;        // [lmax][cap]
     int32_t *ids_tmp;    // [lmax][cap]
     int32_t *iface;      // [lmax][cap]
+    int32_t *refl;       // [lmax][cap]: the refined blocks of each level (parents of the next)
     int32_t *order;      // [lmax][cap] solver launch order per level (Morton)
     int32_t *solidl;     // [lmax][cap] leaf blocks next to a solid block, per level
     int32_t *gap;        // [cap]

@@ -103,6 +103,7 @@ void make_layout(const amr_config *c, Layout *L) {
     L->ids = take(lmax * cap * 4);
     L->ids_tmp = take(lmax * cap * 4);
     L->iface = take(lmax * cap * 4);
+    L->refl = take(lmax * cap * 4);
     L->order = take(lmax * cap * 4);
     L->force = take(cap * 3 * 8);
     L->solidl = take(lmax * cap * 4);
@@ -250,6 +251,7 @@ amr_status refresh_counts(amr_handle *h) {
     for (int L = 0; L < kMaxLevels; L++) {
         h->nids[L] = L < h->lmax ? dc.nids[L] : 0;
         h->niface[L] = L < h->lmax ? dc.niface[L] : 0;
+        h->nref[L] = L < h->lmax ? dc.nref[L] : 0;
         h->nsolid[L] = L < h->lmax ? dc.nsolid[L] : 0;
         h->ghost_w[L] = L < h->lmax ? (double)dc.ghost_w[L] : 0.0;
         h->avg_w[L] = L < h->lmax ? (double)dc.avg_w[L] : 0.0;
@@ -352,6 +354,7 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
     c.ids = (int32_t *)(a + lay.ids);
     c.ids_tmp = (int32_t *)(a + lay.ids_tmp);
     c.iface = (int32_t *)(a + lay.iface);
+    c.refl = (int32_t *)(a + lay.refl);
     c.order = (int32_t *)(a + lay.order);
     c.m.force = (double *)(a + lay.force);
     c.solidl = (int32_t *)(a + lay.solidl);
@@ -533,7 +536,7 @@ amr_status amr_tag(amr_t *h, const amr_tag_params *p, const int8_t *tags_in, int
     const bool vort = !tags_in && (p->kind == AMR_TAG_VORTICITY_REL || p->kind == AMR_TAG_LADDER);
     const bool averaged = vort && h->sync_velocity;
     for (int L = h->lmax - 2; L >= 0; L--)
-        launch_average(c, c.ids + L * cap, h->nids[L], level_params(h), 1, averaged ? c.U : nullptr);
+        launch_average(c, c.refl + L * cap, h->nref[L], level_params(h), 1, averaged ? c.U : nullptr);
     if ((ms = mark(h, 1)) != AMR_OK) return ms;
     for (int L = 0; L <= h->lmax - 2; L++)
         if (h->niface[L] > 0) launch_interp(c, c.iface + L * cap, h->niface[L], level_params(h), 0);

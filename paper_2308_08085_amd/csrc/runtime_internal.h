@@ -24,7 +24,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     size_t f[2], nbr, nbrc, X, level, status, tag, ldes, viol, bflag, gmask, imask;
-    size_t ids, ids_tmp, iface, order, force, solidl, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
+    size_t ids, ids_tmp, iface, refl, order, force, solidl, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
     size_t crit, part4, solid, solid_list, ctr, staging, staging_bytes, total, hid, U, parent, fresh;
 };
 
@@ -38,7 +38,7 @@ struct amr_handle {
     Layout lay;
     int lmax;
     int device;  // the GPU current at creation
-    int nids[kMaxLevels], niface[kMaxLevels], nsolid[kMaxLevels];
+    int nids[kMaxLevels], niface[kMaxLevels], nsolid[kMaxLevels], nref[kMaxLevels];
     double ghost_w[kMaxLevels], avg_w[kMaxLevels];  // cells the grid communication of each level moves
     int gtop;
     int par[kMaxLevels];
