@@ -253,6 +253,17 @@ amr_status lbm_step(amr_t *h, int32_t n_coarse_steps, uint32_t flags);
  *                          follows leaves alone), and the velocity pass covers only the rest;
  *                          0 = the velocity pass computes every velocity.  Criterion values
  *                          and tags do not depend on it; SET accepts 0 or 1 (else AMR_ERR_ARG)
+ *   AMR_FIELD_SKIP_PARENTS GET/SET int32[1]: 0 (the default) = every sweep of level L
+ *                          advances every block of the level's ID set (Sec. "Grid Advancement");
+ *                          1 = it leaves out the refined blocks none of whose children has an
+ *                          N_SKIP link.  Under linear interpolation nothing a leaf reads depends
+ *                          on those blocks' cells before the next synchronisation (amr_tag)
+ *                          averages them again, so leaf cells, output fields, forces and tags
+ *                          are unchanged bit for bit; the skipped blocks' own cells (and cells of
+ *                          neighbouring parents away from any coarse leaf) hold stale values
+ *                          until then.  SET 1 needs linear interpolation (else AMR_ERR_ARG); SET
+ *                          re-captures the step graphs when the value changes.  Batch steps
+ *                          always advance every block.
  *   AMR_FIELD_KERNEL_STATS GET double[3][4]: for the collide-stream, interpolation and averaging
  *                          kernels: launches, summed event time (ms), blocks processed, and the
  *                          distribution bytes those blocks must move, accumulated over lbm_step
@@ -265,7 +276,8 @@ enum amr_field_kind {
     AMR_FIELD_LEVEL = 5, AMR_FIELD_STATUS = 6, AMR_FIELD_COORD = 7, AMR_FIELD_NBR = 8,
     AMR_FIELD_NBR_CHILD = 9, AMR_FIELD_IDSET = 10, AMR_FIELD_GAP = 11, AMR_FIELD_COUNTS = 12,
     AMR_FIELD_MASS_MOM = 13, AMR_FIELD_CRIT = 14, AMR_FIELD_PARITY = 15, AMR_FIELD_KERNEL_STATS = 16,
-    AMR_FIELD_FORCE = 17, AMR_FIELD_FORCE_ON = 18, AMR_FIELD_STREAM_BYTES = 19, AMR_FIELD_SYNC_VELOCITY = 20
+    AMR_FIELD_FORCE = 17, AMR_FIELD_FORCE_ON = 18, AMR_FIELD_STREAM_BYTES = 19, AMR_FIELD_SYNC_VELOCITY = 20,
+    AMR_FIELD_SKIP_PARENTS = 21
 };
 amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf, uint64_t bytes);
 

@@ -20,7 +20,7 @@ STORAGE = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3, "bf16s": 4}
 AMR_GET, AMR_SET = 0, 1
 (F_N_OUT, F_CELLS, F_RHO_U, F_F, F_BLOCK_F, F_LEVEL, F_STATUS, F_COORD, F_NBR, F_NBR_CHILD, F_IDSET, F_GAP,
  F_COUNTS, F_MASS_MOM, F_CRIT, F_PARITY, F_KERNEL_STATS, F_FORCE, F_FORCE_ON, F_STREAM_BYTES,
- F_SYNC_VELOCITY) = range(21)
+ F_SYNC_VELOCITY, F_SKIP_PARENTS) = range(22)
 AMR_CHECK_FINITE, AMR_USE_GRAPH, AMR_PROFILE = 1, 2, 4
 TAG_VORTICITY_REL, TAG_DISTANCE, TAG_LADDER = 0, 1, 2
 COLLIDE_BGK, COLLIDE_MRT, COLLIDE_MRT_MFMA = 0, 1, 2
@@ -260,6 +260,13 @@ class AmrLbm:
         if on is not None:
             self._fields(AMR_SET, F_SYNC_VELOCITY, np.array([1 if on else 0], np.int32))
         return bool(self._fields(AMR_GET, F_SYNC_VELOCITY, np.zeros(1, np.int32))[0])
+
+    def skip_parents(self, on=None):
+        """whether sweeps leave out refined blocks none of whose children has an
+        N_SKIP link (linear interpolation); with `on`, switch it first"""
+        if on is not None:
+            self._fields(AMR_SET, F_SKIP_PARENTS, np.array([1 if on else 0], np.int32))
+        return bool(self._fields(AMR_GET, F_SKIP_PARENTS, np.zeros(1, np.int32))[0])
 
     def stream_bytes(self, value=None):
         """store policy: sweeps writing more than this many bytes use non-temporal

@@ -10,7 +10,8 @@ struct DevCounters {
     int32_t nids[kMaxLevels];
     int32_t niface[kMaxLevels];
     int32_t nsolid[kMaxLevels];
-    int32_t nref[kMaxLevels];  // refined blocks per level (list refl)
+    int32_t nref[kMaxLevels];    // refined blocks per level (list refl)
+    int32_t nsweep[kMaxLevels];  // blocks per level in the sweep list
     int32_t gtop;
     int32_t n_ref, n_coa, n_rev;
     int32_t nfreed;
@@ -41,6 +42,8 @@ struct Ctx {
     int32_t *ids_tmp;    // [lmax][cap]
     int32_t *iface;      // [lmax][cap]
     int32_t *refl;       // [lmax][cap]: the refined blocks of each level (parents of the next)
+    int32_t *sweep;      // [lmax][cap]: the launch order without refined blocks none of whose
+                         // children has an N_SKIP link
     int32_t *order;      // [lmax][cap] solver launch order per level (Morton)
     int32_t *solidl;     // [lmax][cap] leaf blocks next to a solid block, per level
     int32_t *gap;        // [cap]

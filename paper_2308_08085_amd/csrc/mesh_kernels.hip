@@ -238,7 +238,7 @@ __global__ void k_init_ids(const int8_t *bins, const int32_t *rank, int cap, int
     if (B == 0) {
         ctr->nids[0] = ctr->totals[0];
         for (int L = 1; L < kMaxLevels; L++) ctr->nids[L] = 0;
-        for (int L = 0; L < kMaxLevels; L++) ctr->niface[L] = ctr->nref[L] = 0;
+        for (int L = 0; L < kMaxLevels; L++) ctr->niface[L] = ctr->nref[L] = ctr->nsweep[L] = 0;
         ctr->gtop = cap - nroot;
         ctr->n_ref = ctr->n_coa = ctr->n_rev = ctr->nfreed = 0;
         ctr->wmax_bits = 0;
@@ -551,7 +551,8 @@ __global__ void k_bins_keep(const DevMesh m, const int32_t *ids, const DevCounte
         const int B = ids[e];
         if (mode == 0) b = m.status[B] != ST_REMOVE ? (int8_t)L : (int8_t)-1;
         else if (mode == 1) b = (m.bflag[B] & BF_PARENT_MASK) ? (int8_t)L : (int8_t)-1;
-        else b = is_refined(m.status[B]) ? (int8_t)L : (int8_t)-1;
+        else if (mode == 2) b = is_refined(m.status[B]) ? (int8_t)L : (int8_t)-1;
+        else b = (is_refined(m.status[B]) && !(m.bflag[B] & BF_PARENT_MASK)) ? (int8_t)-1 : (int8_t)L;
     }
     bins[e] = b;
 }
@@ -565,7 +566,8 @@ __global__ void k_compact(const int8_t *bins, const int32_t *rank, const int32_t
 }
 
 // copy back the compacted lists; the new sizes are the scan totals
-// which: 0 = interface parents (niface), 1 = ID sets (nids), 2 = refined blocks (nref)
+// which: 0 = interface parents (niface), 1 = ID sets (nids), 2 = refined blocks (nref),
+// 3 = sweep lists (nsweep)
 __global__ void k_copy_lists(const int32_t *src, int32_t *dst, int cap, int lmax, DevCounters *ctr, int which) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)lmax * cap;
@@ -577,6 +579,7 @@ __global__ void k_copy_lists(const int32_t *src, int32_t *dst, int cap, int lmax
         for (int L = 0; L < lmax; L++) {
             if (which == 1) ctr->nids[L] = ctr->totals[L];
             else if (which == 2) ctr->nref[L] = ctr->totals[L];
+            else if (which == 3) ctr->nsweep[L] = ctr->totals[L];
             else ctr->niface[L] = ctr->totals[L];
         }
     }
@@ -824,6 +827,13 @@ void masks_and_lists(const Ctx &c) {
     run_scan(c, c.bins, cap, c.m.lmax);
     k_solid_lists<<<grid_for(cap), 256, 0, c.stream>>>(c.m, c.bins, c.rank, c.solidl, c.ctr);
     build_order<Dd>(c);
+    // sweep lists: the launch order of each level without the refined blocks
+    // none of whose children has an N_SKIP link (bins over the order lists,
+    // which hold the same blocks as the ID sets)
+    k_bins_keep<<<grid_for(tot), 256, 0, c.stream>>>(c.m, c.order, c.ctr, c.bins, 3);
+    run_scan(c, c.bins, tot, c.m.lmax);
+    k_compact<<<grid_for(tot), 256, 0, c.stream>>>(c.bins, c.rank, c.order, c.ids_tmp, cap, tot);
+    k_copy_lists<<<grid_for(tot), 256, 0, c.stream>>>(c.ids_tmp, c.sweep, cap, c.m.lmax, c.ctr, 3);
     k_target_reset<<<1, 64, 0, c.stream>>>(c.ctr);
     k_target_cells<Dd><<<dim3(grid_for(cap), c.m.lmax), 256, 0, c.stream>>>(c.m, c.iface, c.ctr);
 }

@@ -104,6 +104,7 @@ void make_layout(const amr_config *c, Layout *L) {
     L->ids_tmp = take(lmax * cap * 4);
     L->iface = take(lmax * cap * 4);
     L->refl = take(lmax * cap * 4);
+    L->sweep = take(lmax * cap * 4);
     L->order = take(lmax * cap * 4);
     L->force = take(cap * 3 * 8);
     L->solidl = take(lmax * cap * 4);
@@ -179,16 +180,31 @@ static bool small_level(const amr_handle *h, int L) {
     return h->nids[L] <= (h->c.dim == 3 ? 16384 : 65536);  // blocks of 64 / 16 cells
 }
 
+// The blocks a sweep of level L processes, in launch order: every block of the
+// level's ID set (Sec. "Grid Advancement"), or with AMR_FIELD_SKIP_PARENTS all
+// but the refined blocks none of whose children has an N_SKIP link.  Such a
+// deep parent touches no coarser leaf: its stale cells reach only neighbouring
+// parents, on their sides away from any coarse leaf, where the interface
+// averaging of every step stops them before the cells that linear
+// interpolation reads; the next synchronisation averages them all again.
+// Leaf results are unchanged bit for bit (tested).
+static const int32_t *sweep_list(const amr_handle *h, int L, int *n) {
+    const size_t at = (size_t)L * h->c.m.cap;
+    *n = h->skip_parents ? h->nsweep[L] : h->nids[L];
+    return (h->skip_parents ? h->c.sweep : h->c.order) + at;
+}
+
 // fused: the sweep was launched together with the ghost interpolation into
 // level L+1 (launch_interp_collide); exchanged: that launch also added the
 // momentum exchange
 void collide_stream(amr_handle *h, int L, bool fused = false, bool exchanged = false) {
     const LevelParams lp = level_params(h);
     const bool exchange = h->force_on && h->nsolid[L] > 0;
+    int n = 0;
+    const int32_t *list = sweep_list(h, L, &n);
     if (!fused)
-        timed_launch(h, 0, h->nids[L], L, [&] {
-            exchanged = launch_collide_stream(h->c, h->c.order + (size_t)L * h->c.m.cap, h->nids[L], L, lp, h->bc,
-                                              exchange && join_launches(h));
+        timed_launch(h, 0, n, L, [&] {
+            exchanged = launch_collide_stream(h->c, list, n, L, lp, h->bc, exchange && join_launches(h));
         });
     h->par[L] ^= 1;
     // momentum exchange with solid blocks, from the buffer just written
@@ -207,8 +223,10 @@ void step_level(amr_handle *h, int L) {
     bool exchanged = false;
     if (fuse) {
         const LevelParams lp = level_params(h);
-        exchanged = launch_interp_collide(h->c, h->c.iface + L * cap, h->niface[L], h->c.order + L * cap, h->nids[L],
-                                          L, lp, h->bc, h->force_on && h->nsolid[L] > 0);
+        int n = 0;
+        const int32_t *list = sweep_list(h, L, &n);
+        exchanged = launch_interp_collide(h->c, h->c.iface + L * cap, h->niface[L], list, n, L, lp, h->bc,
+                                          h->force_on && h->nsolid[L] > 0);
     } else if (h->niface[L] > 0) {
         const LevelParams lp = level_params(h);
         timed_launch(h, 1, h->niface[L], L, [&] { launch_interp(h->c, h->c.iface + L * cap, h->niface[L], lp, 0); });
@@ -252,6 +270,7 @@ amr_status refresh_counts(amr_handle *h) {
         h->nids[L] = L < h->lmax ? dc.nids[L] : 0;
         h->niface[L] = L < h->lmax ? dc.niface[L] : 0;
         h->nref[L] = L < h->lmax ? dc.nref[L] : 0;
+        h->nsweep[L] = L < h->lmax ? dc.nsweep[L] : 0;
         h->nsolid[L] = L < h->lmax ? dc.nsolid[L] : 0;
         h->ghost_w[L] = L < h->lmax ? (double)dc.ghost_w[L] : 0.0;
         h->avg_w[L] = L < h->lmax ? (double)dc.avg_w[L] : 0.0;
@@ -355,6 +374,7 @@ amr_status amr_create(const amr_config *cfg, void *dev_arena, uint64_t arena_byt
     c.ids_tmp = (int32_t *)(a + lay.ids_tmp);
     c.iface = (int32_t *)(a + lay.iface);
     c.refl = (int32_t *)(a + lay.refl);
+    c.sweep = (int32_t *)(a + lay.sweep);
     c.order = (int32_t *)(a + lay.order);
     c.m.force = (double *)(a + lay.force);
     c.solidl = (int32_t *)(a + lay.solidl);
@@ -703,6 +723,23 @@ amr_status amr_fields(amr_t *h, int32_t op, int32_t kind, int32_t sim, void *buf
         }
         if (*v != 0 && *v != 1) return fail(AMR_ERR_ARG, "AMR_FIELD_SYNC_VELOCITY takes 0 or 1, not %d", *v);
         h->sync_velocity = *v == 1;
+        return AMR_OK;
+    }
+    if (kind == AMR_FIELD_SKIP_PARENTS) {
+        if (!buf || bytes < 4) return fail(AMR_ERR_ARG, "AMR_FIELD_SKIP_PARENTS needs an int32 buffer");
+        int32_t *v = (int32_t *)buf;
+        if (op == AMR_GET) {
+            *v = h->skip_parents ? 1 : 0;
+            return AMR_OK;
+        }
+        if (*v != 0 && *v != 1) return fail(AMR_ERR_ARG, "AMR_FIELD_SKIP_PARENTS takes 0 or 1, not %d", *v);
+        if (*v == 1 && h->c.m.interp != AMR_INTERP_LINEAR)
+            return fail(AMR_ERR_ARG, "AMR_FIELD_SKIP_PARENTS needs linear interpolation (cubic stencils reach "
+                                     "into neighbouring parents)");
+        if ((*v == 1) != h->skip_parents) {
+            h->skip_parents = *v == 1;
+            drop_graphs(h);  // captured steps hold the sweep lists' counts
+        }
         return AMR_OK;
     }
     if (kind == AMR_FIELD_STREAM_BYTES) {

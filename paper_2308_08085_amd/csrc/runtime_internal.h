@@ -24,7 +24,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     size_t f[2], nbr, nbrc, X, level, status, tag, ldes, viol, bflag, gmask, imask;
-    size_t ids, ids_tmp, iface, refl, order, force, solidl, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
+    size_t ids, ids_tmp, iface, refl, sweep, order, force, solidl, gap, first, rlist, clist, cnt, off, rank, bins, scan_part;
     size_t crit, part4, solid, solid_list, ctr, staging, staging_bytes, total, hid, U, parent, fresh;
 };
 
@@ -38,13 +38,14 @@ struct amr_handle {
     Layout lay;
     int lmax;
     int device;  // the GPU current at creation
-    int nids[kMaxLevels], niface[kMaxLevels], nsolid[kMaxLevels], nref[kMaxLevels];
+    int nids[kMaxLevels], niface[kMaxLevels], nsolid[kMaxLevels], nref[kMaxLevels], nsweep[kMaxLevels];
     double ghost_w[kMaxLevels], avg_w[kMaxLevels];  // cells the grid communication of each level moves
     int gtop;
     int par[kMaxLevels];
     double force_sweeps[kMaxLevels] = {0};  // collide-stream sweeps per level since the force reset
     bool force_on = true;                   // accumulate the momentum exchange every sweep
     bool sync_velocity = true;              // criterion velocities from the synchronisation's averaging
+    bool skip_parents = false;              // sweeps leave out refined blocks without N_SKIP children
     int batches = 0;                        // batches this handle is a member of
     double tau[kMaxLevels];
     BCParams bc;

@@ -491,3 +491,68 @@ def test_criterion_velocities_from_the_averaging(dim, q, storage, kind):
             g._fields(abi.AMR_SET, abi.F_SYNC_VELOCITY, np.array([2], np.int32))
         finally:
             g.close()
+
+
+def _deep_parents(m, dim):
+    """refined blocks none of whose children has an N_SKIP link"""
+    nc = 4 if dim == 2 else 8
+    refined = np.isin(m["status"], [1, 2, 3])
+    n = 0
+    for ids in m["ids"]:
+        for P in ids:
+            if refined[P]:
+                c0 = m["nbrc"][P][0]
+                n += not np.any(m["nbr"][c0:c0 + nc] == -2)
+    return n
+
+
+@pytest.mark.parametrize("dim,q,storage", [(2, 9, "f32s"), (3, 27, "f16s"), (3, 19, "f64")])
+def test_skipping_deep_parents_keeps_leaf_results(dim, q, storage):
+    """AMR_FIELD_SKIP_PARENTS: sweeps that leave out the refined blocks none of
+    whose children has an N_SKIP link give the same leaf cells, output fields,
+    forces, mass, criterion values and tags bit for bit, and after each
+    synchronisation (amr_tag) the same cells everywhere, over near-wall
+    refinement and three vorticity adaptations"""
+    if dim == 2:
+        case = W.cylinder(2, 9, (64, 32), 8, 16, 3, 100.0, storage=storage, cap=3000, seed=9)
+    else:
+        case = W.cylinder(3, q, (32, 16, 16), 4, 8, 3, 100.0, storage=storage, cap=12000, seed=10)
+    runs, deep = [], []
+    for skip in (False, True):
+        g = abi.AmrLbm(case)
+        g.set_root_rho_u(case.initial_rho_u())
+        if skip:
+            assert g.skip_parents(True)
+        for _ in range(case.lmax - 1):
+            g.tag(abi.TAG_DISTANCE, d_spec=case.d_spec, freeze=1)
+            g.adapt()
+        out, most = [], 0
+        for _ in range(3):
+            g.step(8, graph=True)
+            g.step(3, graph=False)
+            m = g.mesh()
+            most = max(most, _deep_parents(m, dim))
+            leaf = m["status"] == 0
+            out += [g.get_block_f_all()[leaf], g.rho_u_out(), g.force(), g.mass_mom()]
+            out += [g.tag(abi.TAG_VORTICITY_REL, theta=0.1), g.crit(), g.get_block_f_all()]
+            g.adapt()
+        runs.append(out)
+        deep.append(most)
+        g.close()
+    assert deep[1] > 0
+    for k, (a, b) in enumerate(zip(runs[0], runs[1])):
+        assert np.array_equal(a, b), k
+
+
+def test_skipping_deep_parents_needs_linear_interpolation():
+    case = W.cavity(3, 19, 16, 3, 300.0, storage="f32s", seed=17)
+    case.interp = 1  # cubic
+    g = abi.AmrLbm(case)
+    try:
+        with pytest.raises(abi.AmrError) as e:
+            g.skip_parents(True)
+        assert e.value.code == abi.AMR_ERR_ARG and not g.skip_parents()
+        with pytest.raises(abi.AmrError):
+            g._fields(abi.AMR_SET, abi.F_SKIP_PARENTS, np.array([2], np.int32))
+    finally:
+        g.close()
