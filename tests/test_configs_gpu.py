@@ -52,10 +52,11 @@ def test_config1_full_schedule_fp64():
     p.assert_parity(1e-12, "config 1 after 1000 coarse steps")
 
 
-def replay(name, storage, all_streaming):
+def replay(name, storage, all_streaming, skip_parents=False):
     """Run the stored schedule `name` on the GPU with the oracle's tags; check
     tags, adaptation counts and mesh digests on the way, return the errors of
-    the sampled output cells and of mass and momentum."""
+    the sampled output cells and of mass and momentum.  skip_parents: sweeps
+    leave out the refined blocks none of whose children has an N_SKIP link."""
     gd = G.load(name)
     meta = json.loads(str(gd["meta"]))
     setup, freeze = G.CASES[name]
@@ -65,6 +66,8 @@ def replay(name, storage, all_streaming):
     g = abi.AmrLbm(case)
     if all_streaming:
         g.stream_bytes(0)
+    if skip_parents:
+        g.skip_parents(True)
     g.set_root_rho_u(case.initial_rho_u())
     k = 0
 
@@ -143,3 +146,15 @@ def test_schedule_fp16_storage_error(name):
     (norm-wise and per cell against the velocity scale)"""
     e = replay(name, "f16s", all_streaming=True)
     assert e["u"] < 2e-2 and e["u_cell"] < 2e-2 and e["f_cell"] < 5e-3 and e["mass"] < 1e-4, e
+
+
+@pytest.mark.parametrize("name", [n for n in SCHEDULES if "cylinder" in n])
+@pytest.mark.parametrize("storage,tol,mass_tol", [("f64", 1e-12, 1e-12), ("f32s", 1e-5, 1e-7)])
+def test_schedule_skipping_deep_parents(name, storage, tol, mass_tol):
+    """sweeps that leave out the refined blocks none of whose children has an
+    N_SKIP link (AMR_FIELD_SKIP_PARENTS) against the oracle's run, which sweeps
+    every block: tags, adaptation counts and mesh digests on the way, sampled
+    output cells, mass and momentum after every period, at the same bars"""
+    e = replay(name, storage, all_streaming=storage != "f64", skip_parents=True)
+    assert_cells(e, tol, name, e["U"])
+    assert e["mass"] < mass_tol and e["momentum"] < (1e-12 if storage == "f64" else 1e-5), e
