@@ -256,7 +256,8 @@ amr_status lbm_step(amr_t *h, int32_t n_coarse_steps, uint32_t flags);
  *   AMR_FIELD_SKIP_PARENTS GET/SET int32[1]: 0 (the default) = every sweep of level L
  *                          advances every block of the level's ID set (Sec. "Grid Advancement");
  *                          1 = it leaves out the refined blocks none of whose children has an
- *                          N_SKIP link.  Under linear interpolation nothing a leaf reads depends
+ *                          N_SKIP link (the paper leaves parents out of the advancement, Sec.
+ *                          "Streaming", and its MLUPS count excludes them).  Under linear interpolation nothing a leaf reads depends
  *                          on those blocks' cells before the next synchronisation (amr_tag)
  *                          averages them again, so leaf cells, output fields, forces and tags
  *                          are unchanged bit for bit; the skipped blocks' own cells (and cells of
